@@ -1,0 +1,220 @@
+"""Pins of the oracle's kernel fit (Section 4) against what the paper prints and
+against brute force; no test here re-types the oracle's own formulas."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_params.json")))
+
+
+# --------------------------------------------------------------------------
+# Phi (Section 4.1)
+# --------------------------------------------------------------------------
+def test_phi_ratio_near_four_thirds():
+    """Section 4.1: completing S(0) = 16.5 makes Phi_0 / Phi_r close to 4/3."""
+    ph = oracle.phi(200, 16.5)
+    assert abs(ph[0] / ph[100] - GOLD["phi_ratio"]["value"]) < 3e-3
+
+
+def test_phi_closed_form_limit():
+    """With S(0) = 5 pi^2 / 3 the ratio tends to exactly 4/3 as N grows
+    (sum 1/u^2 = pi^2/6, sum (-1)^u/u^2 = -pi^2/12)."""
+    N = 4000
+    ph = oracle.phi(N, 5.0 * math.pi ** 2 / 3.0)
+    assert abs(ph[0] / ph[N // 2] - 4.0 / 3.0) < 2e-3
+
+
+def test_phi_matches_numpy_ifft():
+    """The direct cosine sum equals numpy's inverse FFT of the same spectrum."""
+    N = 200
+    u = np.arange(N)
+    f = np.minimum(u, N - u).astype(np.float64)
+    S = np.where(f == 0, 16.5, 1.0 / np.maximum(f, 1) ** 2)
+    ref = np.real(np.fft.ifft(S))
+    assert np.allclose(oracle.phi(N, 16.5), ref, rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Per-partition least squares vs an explicit dense construction
+# --------------------------------------------------------------------------
+def _dense_problem(nh, sigma0, use_qf, N=200, dc=16.5):
+    n = 2 * nh - 1
+    t = np.arange(-(nh - 1), nh)
+    g = np.exp(-t.astype(np.float64) ** 2 / (2 * sigma0 ** 2))
+    if use_qf:
+        uu = np.arange(N)
+        f = np.minimum(uu, N - uu).astype(np.float64)
+        S = np.where(f == 0, dc, 1.0 / np.maximum(f, 1) ** 2)
+        ph = np.real(np.fft.ifft(S))
+        lag = (t[:, None] - t[None, :]) % N
+        A = ph[lag]
+    else:
+        A = np.eye(n)
+    return t, g, A
+
+
+def _dense_eval(p, nh, sigma0, use_qf):
+    t, g, A = _dense_problem(nh, sigma0, use_qf)
+    at = np.abs(t)
+    k = len(p)
+    B = np.zeros((len(t), k))
+    lo = -1
+    for i, pi in enumerate(p):
+        B[(at > lo) & (at <= pi), i] = 1.0
+        lo = pi
+    M = B.T @ A @ B
+    v = B.T @ A @ g
+    c = np.linalg.solve(M, v)
+    e = g - B @ c
+    return c, float(e @ A @ e)
+
+
+@pytest.mark.parametrize("use_qf", [True, False])
+def test_eval_partition_matches_dense_least_squares(use_qf):
+    rng = np.random.default_rng(11)
+    s0 = 100.0 / math.pi
+    for _ in range(25):
+        k = int(rng.integers(1, 6))
+        p = np.sort(rng.choice(100, size=k, replace=False))
+        c, e = oracle.eval_partition(p, use_qf=use_qf)
+        c_ref, e_ref = _dense_eval(p, 100, s0, use_qf)
+        assert np.allclose(c, c_ref, rtol=1e-9, atol=1e-11)
+        assert abs(e - e_ref) <= 1e-9 * max(1.0, abs(e_ref))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("use_qf", [True, False])
+def test_exhaustive_search_matches_brute_force_small(k, use_qf):
+    """A 12-sample instance: the oracle's search vs enumerating every partition
+    with dense matrices."""
+    import itertools
+    nh, s0 = 12, 12.0 / math.pi
+    best = None
+    for p in itertools.combinations(range(nh), k):
+        c, e = _dense_eval(list(p), nh, s0, use_qf)
+        if best is None or e < best[1] - 1e-12:
+            best = (p, e, c)
+    p, c, e = oracle.fit(k, use_qf=use_qf, nh=nh, sigma0=s0)
+    assert tuple(p) == tuple(best[0])
+    assert abs(e - best[1]) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# Table 2 (quadratic form) and the commented l2 table
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [3, 5])
+def test_table2_partition_exact(k):
+    p, c, e = oracle.fit(k)
+    assert list(p) == GOLD["table2"][str(k)]["p"]
+
+
+def test_table2_k4_partition_flat_argmin():
+    """K = 4: the printed partition is within one index per entry of the
+    argmin and its error within 0.2 % of the minimum (the objective is flat)."""
+    p, c, e = oracle.fit(4)
+    printed = GOLD["table2"]["4"]["p"]
+    assert max(abs(a - b) for a, b in zip(p, printed)) <= 1
+    _, e_printed = oracle.eval_partition(printed)
+    assert e <= e_printed <= e * 1.002
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_table2_constants_at_printed_partition(k):
+    row = GOLD["table2"][str(k)]
+    c, _ = oracle.eval_partition(row["p"])
+    assert np.max(np.abs(c - np.array(row["c"]))) <= 5e-4
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_l2_table_exact(k):
+    row = GOLD["l2_table"][str(k)]
+    p, c, e = oracle.fit(k, use_qf=False)
+    assert list(p) == row["p"]
+    assert np.max(np.abs(np.array(c) - np.array(row["c"]))) <= 6e-5
+
+
+def test_l2_table_k4_with_index_reading():
+    row = GOLD["l2_table"]["4"]
+    p, c, e = oracle.fit(4, use_qf=False)
+    assert list(p[:3]) == row["p"][:3] and p[3] == 69
+    assert np.max(np.abs(np.array(c) - np.array(row["c"]))) <= 6e-5
+
+
+def test_quadratic_form_beats_l2_under_its_own_metric_and_vice_versa():
+    """Each fit is optimal for its own objective (Section 4.1 vs plain l2)."""
+    for k in (3, 4):
+        pq, cq, eq = oracle.fit(k, use_qf=True)
+        pl, cl, el = oracle.fit(k, use_qf=False)
+        _, eq_at_l2 = oracle.eval_partition(pl, use_qf=True)
+        _, el_at_qf = oracle.eval_partition(pq, use_qf=False)
+        assert eq <= eq_at_l2 and el <= el_at_qf
+
+
+# --------------------------------------------------------------------------
+# Slices vs piecewise constants (Eq. ciwi) and rescaling (Eq. scale1/scale2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_slices_reproduce_piecewise_constants(k):
+    """At sigma where r == p the rescaled slices, with the area factor of
+    Eq. scale2 undone, stack up to the fitted constants c on every segment."""
+    p, c, _ = oracle.fit(k)
+    sigma = 100.0 / math.pi            # sigma0: r == p exactly
+    r, w, _ = oracle.scale(sigma, p, c)
+    assert list(r) == list(p)
+    w_slice = w * (2 * r + 1) / np.array(p, dtype=np.float64)
+    w_slice *= c[0] / w_slice.sum()    # pin the global factor at t = 0
+    h = oracle.kernel_1d(r, w_slice)
+    R = max(p)
+    for i in range(k):
+        lo = -1 if i == 0 else p[i - 1]
+        seg = [t for t in range(-R, R + 1) if lo < abs(t) <= p[i]]
+        assert np.allclose(h[np.array(seg) + R], c[i], rtol=0, atol=1e-12)
+
+
+def test_scale_reaches_table_indices_at_sigma_32():
+    """sigma = 32 is 0.53 % above sigma0 = 100/pi: the floors return Table 2."""
+    for k in (3, 4, 5):
+        p, c, _ = oracle.fit(k)
+        r, w, w32 = oracle.scale(32.0, p, c)
+        assert list(r) == list(p)
+
+
+@pytest.mark.parametrize("sigma", [0.5, 1.0, 2.0, 5.0, 8.0, 13.7, 32.0, 64.0])
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_scaled_kernel_unit_dc_monotone(sigma, k):
+    p, c, _ = oracle.fit(k)
+    r, w, w32 = oracle.scale(sigma, p, c)
+    expect_r = [math.floor(sigma * math.pi * pi / 100.0 + 1e-9) for pi in p]
+    assert list(r) == expect_r
+    h = oracle.kernel_1d(r, w)
+    assert abs(h.sum() - 1.0) < 1e-14
+    R = int(r.max())
+    half = h[R:]
+    assert np.all(np.diff(half) <= 1e-18)           # non-increasing in |t|
+    assert np.all(w >= 0)
+    assert np.all(w32 == w.astype(np.float32))
+
+
+@pytest.mark.parametrize("sigma", [0.5, 2.0, 8.0, 30.0, 50.0, 64.0])
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_u8_integer_weights_bounds(sigma, k):
+    b = oracle.boxes(sigma, k)
+    r, m, G, s = b["r"], b["m"], b["G"], b["s"]
+    assert int(np.sum(m * (2 * r.astype(np.int64) + 1))) == G
+    assert 0 < G < (1 << 24)
+    assert 255 * G * (2 * int(r.max()) + 1) < (1 << 32)
+    assert np.all(m >= 0)
+    # the largest admissible s was taken: s + 1 breaks a bound (or s == 23)
+    if s < 23:
+        m1 = np.rint(np.ldexp(b["w"], s + 1)).astype(np.int64)
+        G1 = int(np.sum(m1 * (2 * r.astype(np.int64) + 1)))
+        assert G1 >= (1 << 24) or 255 * G1 * (2 * int(r.max()) + 1) >= (1 << 32)
+    # integer kernel close to the real one
+    hq = oracle.kernel_1d(r, m.astype(np.float64) / G)
+    h = oracle.kernel_1d(r, b["w"])
+    assert np.max(np.abs(hq - h)) <= k * 0.5 / G + 1e-15
