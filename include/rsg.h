@@ -1,0 +1,189 @@
+/*
+ * rsg.h -- C ABI of the running-sum Gaussian filter for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The method is Elboher & Werman, "Efficient and Accurate Gaussian Image
+ * Filtering Using Running Sums" (arXiv 1107.4958):
+ *   - a symmetric 1D kernel is a sum of K nested, centred boxes ("weighted
+ *     slices", Section 3.2, Eq. S_i and Eq. ciwi);
+ *   - a 1D pass builds the running sum I of the signal (Section 3.3,
+ *     Eq. alg1) and outputs sum_k w_k (I(x + r_k) - I(x - r_k - 1)) at every
+ *     sample (Eq. indep);
+ *   - a 2D image is filtered along rows, then along the columns of the
+ *     intermediate result (Section 3.4);
+ *   - box half-widths and weights come from an exhaustive fit at
+ *     sigma0 = 100/pi under the quadratic-form error of Section 4.1
+ *     (Eq. mahal, autocorrelation of a 1/f spectrum), rescaled to the
+ *     requested sigma by Eq. scale1 / scale2 (Section 4.2).
+ *
+ * Conventions for every entry point:
+ *   - functions never throw; they return RSG_OK (0) or a negative rsg_status;
+ *     rsg_last_error() gives a message for the last failure on the calling
+ *     thread;
+ *   - images are interleaved H x W x C (C in 1..4), row stride in ELEMENTS
+ *     (>= W*C), element type given by rsg_dtype; output dtype = input dtype;
+ *   - device pointers are HIP device addresses owned by the caller; they must
+ *     stay valid until the work on the given stream (or the server ticket) is
+ *     complete; source and destination must not overlap;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream);
+ *     device work is asynchronous on it: launch errors are returned, faults
+ *     surface at the caller's next synchronisation.
+ */
+#ifndef RSG_H
+#define RSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSG_OK = 0,
+    RSG_EINVAL = -1,        /* bad argument */
+    RSG_ENOMEM = -2,        /* host allocation failed, or request exceeds a budget */
+    RSG_EBUSY = -3,         /* queue full; try again later */
+    RSG_ENOTFOUND = -4,     /* unknown ticket */
+    RSG_EDEVICE = -5,       /* HIP runtime error */
+    RSG_EUNSUPPORTED = -6   /* valid but not supported (e.g. K > 5, REFLECT) */
+} rsg_status;
+
+typedef enum { RSG_U8 = 0, RSG_F32 = 1, RSG_F16 = 2, RSG_BF16 = 3 } rsg_dtype;
+
+/* REPLICATE clamps indices to the image; ZERO treats samples outside as 0.
+ * REFLECT is reserved and returns RSG_EUNSUPPORTED. */
+typedef enum { RSG_REPLICATE = 0, RSG_ZERO = 1, RSG_REFLECT = 2 } rsg_boundary;
+
+#define RSG_MAX_K 5
+
+/* Box parameters for one (sigma, K).
+ *   p, c      the sigma0 fit: inclusive half-widths 0 <= p_1 < ... < p_K <= 99
+ *             of the K segments and their least-squares constants
+ *             (Section 4.2, Table 2), fit_err its quadratic-form error;
+ *   r         half-widths at sigma: r_k = floor(sigma * p_k / sigma0 + 1e-9)
+ *             (Eq. scale1);
+ *   w         slice weights w_k = (c_k - c_{k+1}) p_k / (2 r_k + 1)
+ *             (Eq. scale2, c_{K+1} = 0), normalised so that
+ *             sum_k w_k (2 r_k + 1) = 1; w32 = (float)w;
+ *   m, G, s   integer weights of the exact uint8 path: m_k = rint(w_k 2^s),
+ *             G = sum_k m_k (2 r_k + 1), with s the largest integer in
+ *             [1, 23] such that G < 2^24 and 255 G (2 r_K + 1) < 2^32;
+ *             u8_ok = 0 when no s qualifies (uint8 filtering then fails). */
+typedef struct {
+    int32_t K;
+    int32_t p[RSG_MAX_K];
+    double c[RSG_MAX_K];
+    double fit_err;
+    double sigma;
+    int32_t r[RSG_MAX_K];
+    double w[RSG_MAX_K];
+    float w32[RSG_MAX_K];
+    uint32_t m[RSG_MAX_K];
+    uint64_t G;
+    int32_t s;
+    int32_t u8_ok;
+} rsg_boxes;
+
+/* Fit and rescale the boxes for (sigma, K) on the host, in FP64 (the only
+ * FP64 computation of the library).  The sigma0 search is exhaustive over all
+ * C(100, K) partitions and is cached per K for the life of the process
+ * (thread-safe).  sigma must be finite and > 0; K in 1..5.
+ * Errors: RSG_EINVAL (sigma, K, out == NULL), RSG_EUNSUPPORTED (K > 5). */
+int rsg_fit_boxes(double sigma, int K, rsg_boxes* out);
+
+/* Filter one image: rows by the K boxes, then columns (Sections 3.3-3.4), in
+ * one fused kernel launch on `stream`.  uint8 is computed in exact integers
+ * (uint32 running sums, one rounding at the end: round half up of U / G^2);
+ * FP32 / FP16 / BF16 load as FP32 and accumulate in FP32; FP16 / BF16
+ * results are rounded to nearest even.  Row stride = W*C elements.
+ * Errors: RSG_EINVAL (NULL pointers, H or W < 1, C not in 1..4, bad dtype,
+ * sigma <= 0 or not finite, K not in 1..5), RSG_EUNSUPPORTED (REFLECT,
+ * uint8 with no admissible integer scale, box wider than the kernel limits),
+ * RSG_EDEVICE (launch failure). */
+int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt,
+                     double sigma, int K, rsg_boundary b, void* stream);
+
+/* One image of a batch; strides in elements (0 means W*C). */
+typedef struct {
+    const void* src;
+    void* dst;
+    int32_t H, W, C;
+    int64_t src_stride, dst_stride;
+    rsg_dtype dt;
+    double sigma;
+    int32_t K;
+    rsg_boundary b;
+} rsg_image_desc;
+
+/* Bytes of device workspace rsg_filter_batch needs for these n images.
+ * Errors: as rsg_gauss_filter for any descriptor, RSG_EINVAL (n < 1). */
+int rsg_filter_batch_workspace(const rsg_image_desc* d, int n, size_t* bytes);
+
+/* Filter n images of mixed size, channel count, dtype and sigma in ONE
+ * persistent kernel launch on `stream`.  The caller provides a device
+ * workspace of at least rsg_filter_batch_workspace() bytes (descriptors and
+ * the work list are copied into it asynchronously on `stream`, so the
+ * workspace must not be reused until the stream has passed this call).
+ * Each image's result is bit-identical to rsg_gauss_filter on that image
+ * alone (tile shapes are a function of the image only).
+ * Errors: as rsg_gauss_filter, RSG_ENOMEM (ws_bytes too small). */
+int rsg_filter_batch(const rsg_image_desc* d, int n, void* d_workspace, size_t ws_bytes,
+                     void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of filter requests.                        */
+/* ---------------------------------------------------------------------- */
+typedef struct rsg_server rsg_server;
+
+/* d_arena / arena_bytes: caller-owned device memory the server carves its
+ * per-launch workspaces from.  hbm_budget: admission limit on the sum of the
+ * in-flight requests' image bytes (src + dst); 0 means unlimited.
+ * max_inflight: launches outstanding at once (1..64); n_streams: HIP streams
+ * the server creates (1..8); queue_depth: requests waiting for admission
+ * (>= 1); max_batch: requests per launch (>= 1). */
+typedef struct {
+    void* d_arena;
+    size_t arena_bytes;
+    size_t hbm_budget;
+    int32_t max_inflight;
+    int32_t n_streams;
+    int32_t queue_depth;
+    int32_t max_batch;
+} rsg_server_config;
+
+/* Create a server and its scheduler thread on the current HIP device.
+ * Errors: RSG_EINVAL (bad config), RSG_EDEVICE (stream creation). */
+int rsg_server_create(const rsg_server_config* cfg, rsg_server** out);
+
+/* Queue one request (device-resident src/dst, as rsg_image_desc); never
+ * blocks.  Requests are admitted in arrival order when the HBM budget and an
+ * in-flight slot allow, and batched with whatever else is waiting into one
+ * persistent launch while earlier launches are still running.
+ * Errors: RSG_EINVAL (bad descriptor), RSG_ENOMEM (the request alone exceeds
+ * the HBM budget or the arena), RSG_EBUSY (queue full). */
+int rsg_submit(rsg_server* s, const rsg_image_desc* req, uint64_t* ticket);
+
+/* Timestamps are CLOCK_MONOTONIC nanoseconds. */
+typedef struct {
+    int32_t done;       /* 1 when the result is in dst */
+    int32_t status;     /* RSG_OK or the failure of this request */
+    uint64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;
+} rsg_req_stats;
+
+/* Non-blocking status of a ticket.  A ticket that is done is forgotten after
+ * it has been reported once.  Errors: RSG_ENOTFOUND. */
+int rsg_poll(rsg_server* s, uint64_t ticket, rsg_req_stats* out);
+
+/* Drain all queued and in-flight work, stop the thread, free host state.  The
+ * arena stays the caller's. */
+int rsg_server_destroy(rsg_server* s);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* rsg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSG_H */

@@ -1,0 +1,114 @@
+// C ABI entry points (include/rsg.h).  Marshalling and validation only; the
+// filtering itself runs in rsg_kernels.hip, the fit in rsg_fit.cpp.
+#include "rsg_internal.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace rsg {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int set_error(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+// Plans every image and builds the flat work list of a batched launch.
+int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std::vector<BatchTask>& tasks)
+{
+    if (!d || n < 1) return set_error(RSG_EINVAL, "batch needs n >= 1 descriptors");
+    imgs.resize(n);
+    tasks.clear();
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = plan_image(d[i], &imgs[i]);
+        if (rc != RSG_OK) {
+            std::string msg = g_last_error;
+            return set_error(rc, "image %d: %s", i, msg.c_str());
+        }
+        total += imgs[i].ntasks;
+    }
+    if (total > (int64_t(1) << 30)) return set_error(RSG_EUNSUPPORTED, "batch too large");
+    tasks.reserve(size_t(total));
+    // interleave the images' tasks largest-image-first so long images start
+    // early; per-image results do not depend on the order
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return int64_t(imgs[a].ntasks) * (imgs[a].hs + 2 * imgs[a].R) >
+               int64_t(imgs[b].ntasks) * (imgs[b].hs + 2 * imgs[b].R);
+    });
+    for (int i : order)
+        for (int t = 0; t < imgs[i].ntasks; ++t) tasks.push_back(BatchTask{i, t});
+    return RSG_OK;
+}
+
+}  // namespace rsg
+
+extern "C" {
+
+int rsg_fit_boxes(double sigma, int K, rsg_boxes* out)
+{
+    return rsg::make_boxes(sigma, K, true, out);
+}
+
+int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt, double sigma,
+                     int K, rsg_boundary b, void* stream)
+{
+    rsg_image_desc d;
+    d.src = d_src;
+    d.dst = d_dst;
+    d.H = H;
+    d.W = W;
+    d.C = C;
+    d.src_stride = 0;
+    d.dst_stride = 0;
+    d.dt = dt;
+    d.sigma = sigma;
+    d.K = K;
+    d.b = b;
+    rsg::ImgParams ip;
+    int rc = rsg::plan_image(d, &ip);
+    if (rc != RSG_OK) return rc;
+    return rsg::launch_single(ip, static_cast<hipStream_t>(stream));
+}
+
+int rsg_filter_batch_workspace(const rsg_image_desc* d, int n, size_t* bytes)
+{
+    if (!bytes) return rsg::set_error(RSG_EINVAL, "bytes is NULL");
+    std::vector<rsg::ImgParams> imgs;
+    std::vector<rsg::BatchTask> tasks;
+    int rc = rsg::plan_batch(d, n, imgs, tasks);
+    if (rc != RSG_OK) return rc;
+    *bytes = rsg::batch_workspace_bytes(n, int(tasks.size()));
+    return RSG_OK;
+}
+
+int rsg_filter_batch(const rsg_image_desc* d, int n, void* d_workspace, size_t ws_bytes, void* stream)
+{
+    if (!d_workspace) return rsg::set_error(RSG_EINVAL, "workspace is NULL");
+    std::vector<rsg::ImgParams> imgs;
+    std::vector<rsg::BatchTask> tasks;
+    int rc = rsg::plan_batch(d, n, imgs, tasks);
+    if (rc != RSG_OK) return rc;
+    return rsg::launch_batch(imgs.data(), n, tasks.data(), int(tasks.size()), d_workspace, ws_bytes,
+                             static_cast<hipStream_t>(stream));
+}
+
+const char* rsg_last_error(void)
+{
+    return rsg::g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Host-side dispatch from a planned image (or batch class) to the kernel
+// instantiation for its element type, channel count, scan chunk and tap
+// count.  Included once per element type so the instantiations compile in
+// parallel translation units.
+#pragma once
+
+#include "rsg_device.h"
+
+namespace rsg {
+namespace dispatch {
+
+// Scan-chunk options (samples per lane, multiples of C) per channel count;
+// the planner draws from the same lists.
+template <int C> struct Npls;
+template <> struct Npls<1> { static constexpr int v[4] = {2, 4, 8, 16}; };
+template <> struct Npls<2> { static constexpr int v[4] = {4, 8, 16, 0}; };
+template <> struct Npls<3> { static constexpr int v[4] = {6, 12, 24, 0}; };
+template <> struct Npls<4> { static constexpr int v[4] = {4, 8, 16, 0}; };
+
+inline int set_lds_limit(const void* fn, uint32_t bytes)
+{
+    if (bytes <= 64u * 1024u) return RSG_OK;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) != hipSuccess)
+        return set_error(RSG_EUNSUPPORTED, "device refuses %u bytes of LDS per workgroup", bytes);
+    return RSG_OK;
+}
+
+template <class Tr, int C, int NPL, int KT>
+int launch_one(const ImgParams& ip, hipStream_t st)
+{
+    auto fn = dev::k_single<Tr, C, NPL, KT>;
+    int rc = set_lds_limit(reinterpret_cast<const void*>(fn), ip.lds_bytes);
+    if (rc != RSG_OK) return rc;
+    hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3(kWave), ip.lds_bytes, st, ip);
+    return RSG_OK;
+}
+
+template <class Tr, int C, int NPL>
+int launch_k(const ImgParams& ip, hipStream_t st)
+{
+    switch (ip.kt) {
+    case 3: return launch_one<Tr, C, NPL, 3>(ip, st);
+    case 4: return launch_one<Tr, C, NPL, 4>(ip, st);
+    case 5: return launch_one<Tr, C, NPL, 5>(ip, st);
+    default: return set_error(RSG_EUNSUPPORTED, "no kernel for %d taps", ip.kt);
+    }
+}
+
+template <class Tr, int C>
+int launch_npl(const ImgParams& ip, hipStream_t st)
+{
+    constexpr int n0 = Npls<C>::v[0], n1 = Npls<C>::v[1], n2 = Npls<C>::v[2], n3 = Npls<C>::v[3];
+    if (ip.npl == n0) return launch_k<Tr, C, n0>(ip, st);
+    if (ip.npl == n1) return launch_k<Tr, C, n1>(ip, st);
+    if (ip.npl == n2) return launch_k<Tr, C, n2>(ip, st);
+    if constexpr (n3 != 0)
+        if (ip.npl == n3) return launch_k<Tr, C, n3>(ip, st);
+    return set_error(RSG_EUNSUPPORTED, "no kernel for C=%d npl=%d", C, ip.npl);
+}
+
+template <class Tr>
+int launch_single_t(const ImgParams& ip, hipStream_t st)
+{
+    int rc;
+    switch (ip.C) {
+    case 1: rc = launch_npl<Tr, 1>(ip, st); break;
+    case 2: rc = launch_npl<Tr, 2>(ip, st); break;
+    case 3: rc = launch_npl<Tr, 3>(ip, st); break;
+    case 4: rc = launch_npl<Tr, 4>(ip, st); break;
+    default: return set_error(RSG_EINVAL, "bad channel count %d", ip.C);
+    }
+    if (rc != RSG_OK) return rc;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(RSG_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return RSG_OK;
+}
+
+template <class Tr, int C, int KT>
+int batch_one(const BatchClassLaunch& b, hipStream_t st)
+{
+    constexpr int n0 = Npls<C>::v[0], n1 = Npls<C>::v[1], n2 = Npls<C>::v[2], n3 = Npls<C>::v[3];
+    auto fn = dev::k_batch<Tr, C, KT, n0, n1, n2, n3>;
+    int rc = set_lds_limit(reinterpret_cast<const void*>(fn), b.lds);
+    if (rc != RSG_OK) return rc;
+    hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks, b.d_counter);
+    return RSG_OK;
+}
+
+template <class Tr, int C>
+int batch_k(const BatchClassLaunch& b, hipStream_t st)
+{
+    switch (b.kt) {
+    case 3: return batch_one<Tr, C, 3>(b, st);
+    case 4: return batch_one<Tr, C, 4>(b, st);
+    case 5: return batch_one<Tr, C, 5>(b, st);
+    default: return set_error(RSG_EUNSUPPORTED, "no batch kernel for %d taps", b.kt);
+    }
+}
+
+template <class Tr>
+int launch_batch_t(const BatchClassLaunch& b, hipStream_t st)
+{
+    int rc;
+    switch (b.C) {
+    case 1: rc = batch_k<Tr, 1>(b, st); break;
+    case 2: rc = batch_k<Tr, 2>(b, st); break;
+    case 3: rc = batch_k<Tr, 3>(b, st); break;
+    case 4: rc = batch_k<Tr, 4>(b, st); break;
+    default: return set_error(RSG_EINVAL, "bad channel count %d", b.C);
+    }
+    if (rc != RSG_OK) return rc;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(RSG_EDEVICE, "batch launch failed: %s", hipGetErrorString(e));
+    return RSG_OK;
+}
+
+}  // namespace dispatch
+}  // namespace rsg

@@ -1,0 +1,102 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "rsg.h"
+
+namespace rsg {
+
+// Records the message for rsg_last_error() on this thread; returns `code`.
+int set_error(int code, const char* fmt, ...);
+
+// Section 4.2 sigma0 fit (cached per K) and per-sigma boxes.
+int sigma0_fit(int K, bool quadratic_form, int* p, double* c, double* err);
+int make_boxes(double sigma, int K, bool quadratic_form, rsg_boxes* out);
+extern const double kSigma0Value;
+
+constexpr int kWave = 64;          // CDNA wavefront width; also the strip width in samples
+constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies
+
+// Everything one image's kernel needs; plain data, copied to the device for
+// batched launches and passed by value for single-image launches.
+struct ImgParams {
+    const void* src;
+    void* dst;
+    int64_t src_stride;            // elements per row
+    int64_t dst_stride;
+    int32_t H, W, C, K;
+    int32_t dtype;                 // rsg_dtype
+    int32_t boundary;              // rsg_boundary (REPLICATE or ZERO)
+    int32_t kt;                    // taps in the kernel: max(K, 3) (extra taps carry weight 0)
+    int32_t r[RSG_MAX_K];
+    float wf[RSG_MAX_K];           // FP32 slice weights
+    uint32_t m[RSG_MAX_K];         // uint8 integer weights
+    float dc32;                    // sum_k wf_k (2 r_k + 1): DC gain of the FP32 boxes
+    uint64_t G2;                   // G^2 (uint8 rounding denominator)
+    uint64_t G2half;               // floor(G^2 / 2)
+    float invG2;                   // 1 / G^2 rounded to FP32 (quotient estimate)
+    int32_t R;                     // max r
+    // tile plan
+    int32_t npl;                   // samples per lane in the row scan
+    int32_t G;                     // input rows per group (function of dtype and npl)
+    int32_t hs;                    // output rows per task
+    int32_t L;                     // column ring length = 2R + 1 + G
+    int32_t align;                 // span start alignment (samples)
+    int32_t vec;                   // 1: rows allow vector loads of one chunk
+    int32_t nstrips, nsegs, ntasks;
+    int32_t variant;               // kernel instantiation
+    uint32_t lds_bytes;            // dynamic LDS per wave
+};
+
+// One unit of work of a batched launch.
+struct BatchTask {
+    int32_t img;
+    int32_t task;                  // task index inside the image
+};
+
+// Plan for one image: validates, fits (cached), picks the tile shape.
+int plan_image(const rsg_image_desc& d, ImgParams* ip);
+
+// Launchers (rsg_kernels.hip).
+int launch_single(const ImgParams& ip, hipStream_t stream);
+int launch_single_u8(const ImgParams& ip, hipStream_t stream);
+int launch_single_f32(const ImgParams& ip, hipStream_t stream);
+int launch_single_f16(const ImgParams& ip, hipStream_t stream);
+int launch_single_bf16(const ImgParams& ip, hipStream_t stream);
+// One persistent launch over the tasks of one (dtype, C, kt) class.
+struct BatchClassLaunch {
+    int dtype, C, kt;
+    int grid;
+    uint32_t lds;
+    const ImgParams* d_imgs;
+    const BatchTask* d_tasks;
+    int ntasks;
+    unsigned* d_counter;
+};
+int launch_batch_class(const BatchClassLaunch& b, hipStream_t stream);
+int launch_batch_class_u8(const BatchClassLaunch& b, hipStream_t stream);
+int launch_batch_class_f32(const BatchClassLaunch& b, hipStream_t stream);
+int launch_batch_class_f16(const BatchClassLaunch& b, hipStream_t stream);
+int launch_batch_class_bf16(const BatchClassLaunch& b, hipStream_t stream);
+// Rows per group of the kernel for (dtype, npl): two groups of raw chunks
+// stay within ~64 VGPRs.
+inline int group_rows(int dt, int npl)
+{
+    const int words = (npl * (dt == RSG_U8 ? 1 : (dt == RSG_F32 ? 4 : 2)) + 3) / 4;
+    return words <= 4 ? 8 : (words <= 8 ? 4 : 2);
+}
+// h_stage: optional pinned host buffer of >= batch_workspace_bytes() used to
+// stage the work list (must not be reused before the copy has executed);
+// NULL stages through pageable memory.
+int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, int ntasks,
+                 void* d_ws, size_t ws_bytes, hipStream_t stream, void* h_stage = nullptr);
+size_t batch_workspace_bytes(int nimg, int ntasks);
+
+// Sizes of the element types.
+inline int dtype_size(int dt) { return dt == RSG_U8 ? 1 : (dt == RSG_F32 ? 4 : 2); }
+
+}  // namespace rsg

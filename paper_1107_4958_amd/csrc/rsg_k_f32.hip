@@ -1,0 +1,16 @@
+// Kernel instantiations for one element type (see rsg_device.h).
+#include "rsg_dispatch.h"
+
+namespace rsg {
+
+int launch_single_f32(const ImgParams& ip, hipStream_t stream)
+{
+    return dispatch::launch_single_t<dev::TrF32>(ip, stream);
+}
+
+int launch_batch_class_f32(const BatchClassLaunch& b, hipStream_t stream)
+{
+    return dispatch::launch_batch_t<dev::TrF32>(b, stream);
+}
+
+}  // namespace rsg

@@ -1,0 +1,201 @@
+// Tile planning: validates one image descriptor, fits its boxes (cached) and
+// chooses the scan chunk and segment height of its tasks (strips are 64
+// sample-columns wide: one column per lane).
+//
+// The choice is a pure function of the image's own parameters (dtype, C, H,
+// W, the box half-widths, boundary, pointer alignment), never of the batch it
+// arrives in, so an image filters to the same bits alone or in a mix.  Shapes
+// come from a tuning table (tile-shape buckets measured on the device, see
+// autotune.py) when one is loaded, otherwise from the built-in rule below.
+#include "rsg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace rsg {
+
+namespace {
+
+constexpr uint32_t kLdsLimit = 160u * 1024u;    // gfx950: 160 KiB of LDS per CU
+
+int gcd_i(int a, int b) { while (b) { int t = a % b; a = b; b = t; } return a; }
+int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
+
+// scan-chunk options per channel count (samples per lane, multiples of C);
+// the kernel dispatch instantiates exactly these
+const int* npl_options(int C, int* n)
+{
+    static const int c1[] = {2, 4, 8, 16}, c2[] = {4, 8, 16}, c3[] = {6, 12, 24}, c4[] = {4, 8, 16};
+    switch (C) {
+    case 1: *n = 4; return c1;
+    case 2: *n = 3; return c2;
+    case 3: *n = 3; return c3;
+    default: *n = 3; return c4;
+    }
+}
+
+// Tuning table (text): lines "dtype C rlo rhi hs", '#' starts a comment.
+// The segment height of an image whose largest half-width R lies in
+// [rlo, rhi] is taken from the first matching line.
+struct TuneEntry { int dtype, C, rlo, rhi, hs; };
+std::once_flag g_tune_once;
+std::vector<TuneEntry> g_tune;
+
+void load_tune_table()
+{
+    const char* path = std::getenv("RSG_TUNE_TABLE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t h = line.find('#');
+        if (h != std::string::npos) line.resize(h);
+        std::istringstream is(line);
+        TuneEntry e;
+        if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.hs && e.hs > 0) g_tune.push_back(e);
+    }
+}
+
+bool tuned_hs(int dtype, int C, int R, int* hs)
+{
+    std::call_once(g_tune_once, load_tune_table);
+    for (const auto& e : g_tune)
+        if (e.dtype == dtype && e.C == C && R >= e.rlo && R <= e.rhi) { *hs = e.hs; return true; }
+    return false;
+}
+
+// Built-in segment height: minimise (rounds of resident waves) x (rows each
+// wave streams), i.e. ceil(tasks / resident) * (hs + 2R + 1).
+int default_hs(int H, int nstrips, int R, uint32_t lds)
+{
+    const int per_cu = std::max(1, std::min(16, int(kLdsLimit / std::max(lds, 1u))));
+    const int64_t resident = int64_t(256) * per_cu;
+    int best = 32;
+    int64_t best_cost = -1;
+    for (int hs : {32, 64, 128, 256, 512, 1024, 2048}) {
+        const int h = std::min(hs, H);
+        const int64_t tasks = int64_t(nstrips) * ((H + h - 1) / h);
+        const int64_t rounds = (tasks + resident - 1) / resident;
+        const int64_t cost = rounds * (h + 2 * R + 1);
+        if (best_cost < 0 || cost <= best_cost) { best_cost = cost; best = h; }
+        if (hs >= H) break;
+    }
+    return best;
+}
+
+}  // namespace
+
+int plan_image(const rsg_image_desc& d, ImgParams* ip)
+{
+    if (!d.src || !d.dst) return set_error(RSG_EINVAL, "NULL image pointer");
+    if (d.H < 1 || d.W < 1) return set_error(RSG_EINVAL, "H and W must be >= 1 (got %d x %d)", d.H, d.W);
+    if (d.C < 1 || d.C > 4) return set_error(RSG_EINVAL, "C must be in 1..4 (got %d)", d.C);
+    if (d.dt < RSG_U8 || d.dt > RSG_BF16) return set_error(RSG_EINVAL, "bad dtype %d", int(d.dt));
+    if (d.b == RSG_REFLECT) return set_error(RSG_EUNSUPPORTED, "REFLECT boundary is not supported");
+    if (d.b != RSG_REPLICATE && d.b != RSG_ZERO) return set_error(RSG_EINVAL, "bad boundary %d", int(d.b));
+    const int64_t WC = int64_t(d.W) * d.C;
+    if (WC > (int64_t(1) << 30) || d.H > (1 << 30)) return set_error(RSG_EUNSUPPORTED, "image too large");
+    const int64_t ss = d.src_stride ? d.src_stride : WC;
+    const int64_t ds = d.dst_stride ? d.dst_stride : WC;
+    if (ss < WC || ds < WC) return set_error(RSG_EINVAL, "row stride smaller than W*C");
+    const int es = dtype_size(d.dt);
+    {   // source and destination must not overlap
+        const char* s0 = static_cast<const char*>(d.src);
+        const char* s1 = s0 + (int64_t(d.H - 1) * ss + WC) * es;
+        const char* t0 = static_cast<const char*>(d.dst);
+        const char* t1 = t0 + (int64_t(d.H - 1) * ds + WC) * es;
+        if (s0 < t1 && t0 < s1) return set_error(RSG_EINVAL, "source and destination overlap");
+    }
+
+    rsg_boxes b;
+    int rc = make_boxes(d.sigma, d.K, true, &b);
+    if (rc != RSG_OK) return rc;
+    if (d.dt == RSG_U8 && !b.u8_ok)
+        return set_error(RSG_EUNSUPPORTED, "no integer weight scale for uint8 at sigma=%g K=%d", d.sigma, d.K);
+
+    ImgParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.src = d.src;
+    p.dst = d.dst;
+    p.src_stride = ss;
+    p.dst_stride = ds;
+    p.H = d.H;
+    p.W = d.W;
+    p.C = d.C;
+    p.K = d.K;
+    p.dtype = d.dt;
+    p.boundary = d.b;
+    int R = 0;
+    for (int k = 0; k < d.K; ++k) {
+        p.r[k] = b.r[k];
+        p.wf[k] = b.w32[k];
+        p.m[k] = b.m[k];
+        R = std::max(R, int(b.r[k]));
+    }
+    p.R = R;
+    if (d.dt == RSG_U8) {
+        p.G2 = b.G * b.G;
+        p.G2half = p.G2 / 2;
+        p.invG2 = float(1.0 / double(p.G2));
+    }
+
+    // taps: K < 3 is padded with zero-weight boxes of half-width 0
+    p.kt = std::max(3, d.K);
+    for (int k = d.K; k < p.kt; ++k) { p.r[k] = 0; p.wf[k] = 0.0f; p.m[k] = 0; }
+    {
+        double dc = 0.0;
+        for (int k = 0; k < p.kt; ++k) dc += double(p.wf[k]) * (2.0 * p.r[k] + 1.0);
+        p.dc32 = float(dc);
+    }
+
+    // ---- scan chunk: smallest option whose 64 lanes cover the row span ----
+    const int C = d.C;
+    int nopt = 0;
+    const int* opts = npl_options(C, &nopt);
+    int npl = 0, align = 1;
+    for (int i = 0; i < nopt; ++i) {
+        const int cb = opts[i] * es;                 // chunk bytes
+        const int unit = gcd_i(cb, 16);              // vector load granule
+        const int al = lcm_i(C, std::max(1, unit / es));
+        const int64_t span = int64_t(kWave) + int64_t(2 * R + 1) * C + al - 1;
+        if (span <= int64_t(kWave) * opts[i]) { npl = opts[i]; align = al; break; }
+    }
+    if (!npl)
+        return set_error(RSG_EUNSUPPORTED, "box half-width %d too wide for C=%d (largest row span %d samples)",
+                         R, C, kWave * opts[nopt - 1]);
+    p.npl = npl;
+    p.align = align;
+    {
+        const int unit = gcd_i(npl * es, 16);
+        const uintptr_t sa = reinterpret_cast<uintptr_t>(d.src);
+        p.vec = (sa % unit == 0) && ((ss * es) % unit == 0);
+    }
+    p.G = group_rows(d.dt, npl);
+    p.L = 2 * R + 1 + p.G;
+    p.lds_bytes = uint32_t(4 * (p.G * kWave * npl + p.L * kWave));
+    if (p.lds_bytes > kLdsLimit)
+        return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", p.lds_bytes, kLdsLimit);
+    p.nstrips = int((WC + kWave - 1) / kWave);
+
+    // ---- segment height ----
+    int hs = 0;
+    if (!tuned_hs(d.dt, C, R, &hs)) hs = default_hs(d.H, p.nstrips, R, p.lds_bytes);
+    hs = std::max(1, std::min(hs, d.H));
+    p.hs = hs;
+    p.nsegs = (d.H + hs - 1) / hs;
+    const int64_t nt = int64_t(p.nstrips) * p.nsegs;
+    if (nt > (int64_t(1) << 30)) return set_error(RSG_EUNSUPPORTED, "too many tasks");
+    p.ntasks = int(nt);
+    *ip = p;
+    return RSG_OK;
+}
+
+}  // namespace rsg

@@ -1,0 +1,128 @@
+"""Host-side checks of the C ABI library (no device work): exports, the
+library's own FP64 fit against the oracle's, and argument validation."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rsg():
+    import paper_1107_4958_amd as rsg
+    return rsg
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "rsg.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(rsg_\w+)\s*\(", header, re.M))
+    assert len(declared) == 9
+    rsg = _rsg()
+    lib = ctypes.CDLL(rsg.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(rsg.SYMBOLS)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5])
+def test_library_fit_matches_oracle_fit(K):
+    """Two independent searches (incremental Cholesky vs summed-area table)
+    land on the same partition and constants."""
+    rsg = _rsg()
+    b = rsg.rsg_fit_boxes(8.0, K)
+    p, c, e = oracle.fit(K)
+    assert list(b.p[:K]) == list(p)
+    assert np.allclose(list(b.c[:K]), c, rtol=0, atol=1e-12)
+    # E2 = gAg - v.c cancels ~1e3-sized terms: compare at 1e-9 absolute
+    assert abs(b.fit_err - e) <= 1e-9
+
+
+SIGMAS = [0.5, 0.8, 1.0, 1.7, 2.0, 3.3, 5.0, 8.0, 12.5, 100.0 / math.pi, 32.0, 47.3, 64.0]
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5])
+def test_library_boxes_bit_identical_to_oracle(K):
+    rsg = _rsg()
+    for sigma in SIGMAS:
+        b = rsg.rsg_fit_boxes(sigma, K)
+        o = oracle.boxes(sigma, K)
+        assert list(b.r[:K]) == o["r"].tolist(), sigma
+        # the two least-squares solves agree to ~1e-12; the roundings below must not see it
+        assert np.allclose(list(b.w[:K]), o["w"], rtol=1e-10, atol=0), sigma
+        assert np.array_equal(np.array(b.w32[:K], dtype=np.float32), o["w32"]), sigma
+        if o["m"] is not None:
+            assert b.u8_ok == 1
+            assert list(b.m[:K]) == o["m"].tolist() and b.G == o["G"] and b.s == o["s"], sigma
+        else:
+            assert b.u8_ok == 0
+
+
+def test_fit_boxes_errors():
+    rsg = _rsg()
+    lib = rsg.lib()
+    out = rsg.rsg_boxes()
+    assert lib.rsg_fit_boxes(1.0, 0, ctypes.byref(out)) == rsg.RSG_EINVAL
+    assert lib.rsg_fit_boxes(1.0, 6, ctypes.byref(out)) == rsg.RSG_EUNSUPPORTED
+    assert lib.rsg_fit_boxes(0.0, 3, ctypes.byref(out)) == rsg.RSG_EINVAL
+    assert lib.rsg_fit_boxes(float("nan"), 3, ctypes.byref(out)) == rsg.RSG_EINVAL
+    assert lib.rsg_fit_boxes(-2.0, 3, ctypes.byref(out)) == rsg.RSG_EINVAL
+    assert lib.rsg_fit_boxes(float("inf"), 3, ctypes.byref(out)) == rsg.RSG_EINVAL
+    assert lib.rsg_fit_boxes(1.0, 3, None) == rsg.RSG_EINVAL
+    assert "sigma" in rsg.rsg_last_error() or "NULL" in rsg.rsg_last_error()
+
+
+def test_gauss_filter_rejects_bad_arguments_before_any_device_call():
+    rsg = _rsg()
+    lib = rsg.lib()
+    A, B = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
+    cases = [
+        ((None, B, 8, 8, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, None, 8, 8, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 0, 8, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 8, -1, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 8, 8, 5, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 8, 8, 0, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 8, 8, 1, 7, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 8, 8, 1, rsg.RSG_F32, 0.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 0, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+        ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 6, rsg.RSG_REPLICATE), rsg.RSG_EUNSUPPORTED),
+        ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REFLECT), rsg.RSG_EUNSUPPORTED),
+        ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 3, 9), rsg.RSG_EINVAL),
+        ((A, ctypes.c_void_p(0x100000 + 64), 8, 8, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
+    ]
+    for args, want in cases:
+        assert lib.rsg_gauss_filter(*args, None) == want, args
+        assert rsg.rsg_last_error() != ""
+
+
+def test_batch_workspace_is_host_only_and_validates():
+    rsg = _rsg()
+    d = rsg.rsg_image_desc()
+    d.src, d.dst = 0x100000, 0x90000000
+    d.H, d.W, d.C = 1000, 700, 3
+    d.src_stride = d.dst_stride = 0
+    d.dt, d.sigma, d.K, d.b = rsg.RSG_U8, 6.0, 4, rsg.RSG_REPLICATE
+    n = rsg.rsg_filter_batch_workspace([d, d])
+    assert n > 0
+    bad = rsg.rsg_image_desc.from_buffer_copy(d)
+    bad.C = 9
+    with pytest.raises(rsg.RsgError) as ei:
+        rsg.rsg_filter_batch_workspace([d, bad])
+    assert ei.value.code == rsg.RSG_EINVAL and "image 1" in str(ei.value)
+    with pytest.raises(rsg.RsgError):
+        rsg.rsg_filter_batch_workspace([])
+
+
+def test_uint8_unsupported_where_no_integer_scale_exists():
+    rsg = _rsg()
+    b = rsg.rsg_fit_boxes(2000.0, 5)         # r_K = 5340: no s >= 1 keeps 255 G (2 r + 1) below 2^32
+    assert b.u8_ok == 0
+    lib = rsg.lib()
+    rc = lib.rsg_gauss_filter(ctypes.c_void_p(0x100000), ctypes.c_void_p(0x90000000), 8, 8, 1, rsg.RSG_U8,
+                              2000.0, 5, rsg.RSG_REPLICATE, None)
+    assert rc == rsg.RSG_EUNSUPPORTED

@@ -1,0 +1,148 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: uint8 bit-exact against the exact-integer oracle; FP32 max|err| /
+max|ref| <= 1e-5 against the FP64 oracle run with the same FP32 weights;
+FP16 / BF16 within one unit in the last place of the oracle's FP64 result
+rounded to the storage format (FP32 accumulation error is far below half an
+ulp of the output, so only ties decided by it can differ)."""
+import numpy as np
+import pytest
+
+import oracle
+import synthimg
+from gpu_util import decode, gpu_filter, half_ulp_diff, rel_max_err
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+def _check(img, dtype, sigma, K, boundary):
+    b = oracle.boxes(sigma, K)
+    out = gpu_filter(img, dtype, sigma, K, boundary)
+    if dtype == "u8":
+        ref = oracle.box_filter_u8(img, b["r"], b["m"], b["G"], boundary)
+        bad = np.argwhere(out != ref)
+        assert bad.size == 0, "uint8 mismatch at %s: gpu %s oracle %s" % (
+            bad[:3].tolist(), out[tuple(bad[0])], ref[tuple(bad[0])])
+        return 0.0
+    ref = oracle.box_filter(decode(img, dtype), b["r"], b["w32"].astype(np.float64), boundary)
+    if dtype == "f32":
+        e = rel_max_err(out, ref)
+        assert e <= FP32_TOL, "FP32 rel err %.3g" % e
+        return e
+    d = half_ulp_diff(out, ref, dtype)
+    assert d <= 1, "%s differs by %d ulp" % (dtype, d)
+    return d
+
+
+# (H, W, C, sigma, K): ragged sizes, boxes wider than the image, every C and K
+SHAPES = [
+    (1, 1, 1, 2.0, 3), (1, 37, 1, 1.0, 3), (41, 1, 1, 1.5, 4), (3, 5, 1, 8.0, 5),
+    (17, 300, 1, 5.0, 3), (300, 17, 1, 5.0, 3), (64, 64, 1, 2.0, 1), (65, 129, 1, 3.0, 2),
+    (200, 333, 1, 8.0, 3), (97, 250, 2, 4.0, 4), (61, 211, 3, 6.0, 5), (70, 90, 4, 2.5, 3),
+    (130, 77, 3, 20.0, 4), (257, 259, 1, 32.0, 5), (33, 520, 1, 0.5, 5), (129, 1000, 1, 12.0, 3),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+@pytest.mark.parametrize("boundary", [oracle.REPLICATE, oracle.ZERO])
+@pytest.mark.parametrize("H,W,C,sigma,K", SHAPES)
+def test_parity_shapes(dtype, boundary, H, W, C, sigma, K):
+    img = synthimg.image(H, W, C, dtype, seed=H * 31 + W)
+    _check(img, dtype, sigma, K, boundary)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("H,W,C,sigma,K", SHAPES[::2])
+def test_parity_half_formats(dtype, H, W, C, sigma, K):
+    img = synthimg.image(H, W, C, dtype, seed=H * 7 + W)
+    _check(img, dtype, sigma, K, oracle.REPLICATE)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8", "f16", "bf16"])
+def test_plain_method_512(dtype):
+    """512 x 512 single channel, sigma 5, K 3, replicate: the whole image."""
+    img = synthimg.image(512, 512, 1, dtype, seed=1)
+    _check(img, dtype, 5.0, 3, oracle.REPLICATE)
+
+
+@pytest.mark.parametrize("sigma,K", [(2.0, 3), (8.0, 4), (32.0, 5), (64.0, 5)])
+def test_u8_constant_and_impulse(sigma, K):
+    b = oracle.boxes(sigma, K)
+    for v in (0, 1, 128, 255):
+        img = np.full((150, 190), v, dtype=np.uint8)
+        assert np.all(gpu_filter(img, "u8", sigma, K) == v)
+    n = 2 * int(b["r"].max()) + 9
+    img = np.zeros((n, n + 3), dtype=np.uint8)
+    img[n // 2, n // 2] = 255
+    out = gpu_filter(img, "u8", sigma, K, oracle.ZERO)
+    ref = oracle.box_filter_u8(img, b["r"], b["m"], b["G"], oracle.ZERO)
+    assert np.array_equal(out, ref)
+
+
+def test_row_then_column_equals_transposed_u8():
+    img = synthimg.image(300, 211, 1, "u8", seed=5)
+    a = gpu_filter(img, "u8", 6.0, 4)
+    t = gpu_filter(np.ascontiguousarray(img.T), "u8", 6.0, 4).T
+    assert np.array_equal(a, t)
+
+
+def test_deterministic_repeat():
+    img = synthimg.image(700, 900, 1, "f32", seed=8)
+    a = gpu_filter(img, "f32", 8.0, 3)
+    b = gpu_filter(img, "f32", 8.0, 3)
+    assert np.array_equal(a, b)
+
+
+# --------------------------------------------------------------------------
+# Full-size configurations: sampled outputs computed one by one by the oracle
+# --------------------------------------------------------------------------
+def _sample_points(H, W, C, n, seed):
+    rng = np.random.default_rng(seed)
+    ys = list(rng.integers(0, H, n))
+    xs = list(rng.integers(0, W, n))
+    # corners and edges
+    for y in (0, 1, H // 2, H - 2, H - 1):
+        for x in (0, 1, W // 2, W - 2, W - 1):
+            ys.append(max(0, y))
+            xs.append(max(0, x))
+    ys = np.array(ys) % H
+    xs = np.array(xs) % W
+    cs = rng.integers(0, C, len(ys))
+    return ys, xs, cs
+
+
+def _sampled_check(H, W, C, dtype, sigma, K, npts=1500, seed=0):
+    b = oracle.boxes(sigma, K)
+    img = synthimg.image(H, W, C, dtype, seed=seed)
+    out = gpu_filter(img, dtype, sigma, K)
+    if out.ndim == 2:
+        out = out[..., None]
+    img3 = img if img.ndim == 3 else img[..., None]
+    ys, xs, cs = _sample_points(H, W, C, npts, seed + 1)
+    if dtype == "u8":
+        ref = oracle.box_filter_u8_points(img3, b["r"], b["m"], b["G"], ys, xs, cs)
+        got = out[ys, xs, cs]
+        assert np.array_equal(got, ref), "uint8 sampled mismatch"
+        return
+    ref = oracle.box_filter_points(decode(img3, dtype), b["r"], b["w32"].astype(np.float64), ys, xs, cs)
+    got = out[ys, xs, cs]
+    if dtype == "f32":
+        den = float(np.max(np.abs(decode(img3, dtype))))   # max|ref| <= max|input| (unit DC gain)
+        assert float(np.max(np.abs(got - ref))) / den <= FP32_TOL
+    else:
+        assert half_ulp_diff(got, ref, dtype) <= 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+@pytest.mark.parametrize("sigma", [2.0, 8.0, 32.0])
+@pytest.mark.parametrize("K", [3, 4, 5])
+def test_at_scale_4096(dtype, sigma, K):
+    _sampled_check(4096, 4096, 1, dtype, sigma, K, npts=800, seed=2)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8", "f16", "bf16"])
+@pytest.mark.parametrize("sigma", [4.0, 64.0])
+def test_precision_8192(dtype, sigma):
+    _sampled_check(8192, 8192, 1, dtype, sigma, 5, npts=500, seed=4)
