@@ -1,23 +1,27 @@
 // Device code of the fused running-sum Gaussian filter for gfx950 (MI355X).
 //
 // One 64-lane wave owns one task: a strip of 64 consecutive sample-columns
-// (lane l owns column s0 + l) and a segment of hs output rows of one image.
-// It streams down the image in groups of G input rows:
+// (lane c owns column s0 + c in the column pass) and a segment of hs output
+// rows of one image.  It streams down the image in groups of G input rows:
 //
-//   row pass (Section 3.3, Eq. alg1 / indep, along x), per input row:
-//     the row span [s0 - (R+1)C, s0 + 64 + RC) is loaded lane-contiguous
-//     (lane l holds NPL consecutive samples; border samples extended by
-//     replicate or zero), its running sum I is built with a serial per-lane
-//     scan per channel plus a DPP scan of the lane totals and written to LDS;
-//     each lane then takes T(s) = sum_k w_k (I(s + r_k C) - I(s - (r_k+1) C)).
-//   column pass (Section 3.4, the same along y):
-//     each lane adds T to its running column sum J, writes J to an LDS ring
-//     holding the last 2R + 1 + G rows and emits, for the row R behind the
-//     newest, out = sum_k w_k (J(y + r_k) - J(y - r_k - 1)).
+//   row pass (Section 3.3, Eq. alg1 / indep, along x): the wave splits into
+//     G = 64 / SEG segments of SEG lanes; segment j takes input row
+//     (group start + j), lane q of the segment holds NPL consecutive samples
+//     of the row span [s0 - (R+1)C, s0 + 64 + RC) (border samples replicated
+//     or zero).  The running sum I of each row is a serial scan inside the
+//     lane plus a DPP scan of the lane totals across the segment; the G rows
+//     of running sums go to LDS.  Then every lane (now: a column) takes
+//     T(s) = sum_k w_k (I(s + r_k C) - I(s - (r_k+1) C)) for each row.
+//   column pass (Section 3.4, the same along y): each lane adds T to its
+//     running column sum J, writes J to an LDS ring holding the last
+//     L >= 2R + 1 + G rows and emits, for the row R behind the newest,
+//     out = sum_k w_k (J(y + r_k) - J(y - r_k - 1)).
 //
-// All G rows of a group are scanned before one barrier, so the LDS reads of
-// the box differences issue back to back; the next group's global loads are
-// in flight while the current group is processed.
+// Global memory is addressed through buffer descriptors with row offsets in
+// SGPRs: border zero-padding and dropped stores (rows outside the task, lanes
+// past the image) use an out-of-range offset instead of branches, so every
+// group issues a fixed number of memory instructions and the next groups'
+// loads stay in flight while the current one is processed.
 //
 // FP32 / FP16 / BF16 accumulate in FP32.  Running sums are tile-local and
 // offset: each row subtracts its first span sample (added back through the
@@ -33,19 +37,20 @@
 
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "rsg_internal.h"
 
 namespace rsg {
 namespace dev {
 
 // --------------------------------------------------------------------------
-// DPP wave scans (gfx9 row_shr / row_bcast / wave_shr controls)
+// DPP (gfx9 row_shr / row_bcast controls)
 // --------------------------------------------------------------------------
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowShr2 = 0x112;
 constexpr int kDppRowShr4 = 0x114;
 constexpr int kDppRowShr8 = 0x118;
-constexpr int kDppWaveShr1 = 0x138;
 constexpr int kDppRowBcast15 = 0x142;
 constexpr int kDppRowBcast31 = 0x143;
 
@@ -63,17 +68,17 @@ template <class T> __device__ __forceinline__ T frombits(uint32_t v);
 template <> __device__ __forceinline__ uint32_t frombits<uint32_t>(uint32_t v) { return v; }
 template <> __device__ __forceinline__ float frombits<float>(uint32_t v) { return __uint_as_float(v); }
 
-// Exclusive prefix over the 64 lanes (lane 0 gets 0).
-template <class T>
-__device__ __forceinline__ T wave_exclusive_scan(T x)
+// Inclusive scan across segments of SEG lanes (16, 32 or 64).
+template <int SEG, class T>
+__device__ __forceinline__ T segment_inclusive_scan(T x)
 {
     x = addv(x, frombits<T>(dpp<kDppRowShr1, 0xf>(bits(x))));
     x = addv(x, frombits<T>(dpp<kDppRowShr2, 0xf>(bits(x))));
     x = addv(x, frombits<T>(dpp<kDppRowShr4, 0xf>(bits(x))));
     x = addv(x, frombits<T>(dpp<kDppRowShr8, 0xf>(bits(x))));
-    x = addv(x, frombits<T>(dpp<kDppRowBcast15, 0xa>(bits(x))));
-    x = addv(x, frombits<T>(dpp<kDppRowBcast31, 0xc>(bits(x))));
-    return frombits<T>(dpp<kDppWaveShr1, 0xf>(bits(x)));
+    if constexpr (SEG >= 32) x = addv(x, frombits<T>(dpp<kDppRowBcast15, 0xa>(bits(x))));
+    if constexpr (SEG >= 64) x = addv(x, frombits<T>(dpp<kDppRowBcast31, 0xc>(bits(x))));
+    return x;
 }
 
 // --------------------------------------------------------------------------
@@ -85,7 +90,6 @@ struct TrU8 {
     static constexpr int kSize = 1;
     static constexpr bool kInt = true;
     __device__ static Acc unpack(const uint32_t* w, int i) { return (w[i >> 2] >> (8 * (i & 3))) & 0xffu; }
-    __device__ static uint32_t pack_raw(In v, int i) { return uint32_t(v) << (8 * (i & 3)); }
 };
 struct TrF32 {
     using In = float;
@@ -93,8 +97,6 @@ struct TrF32 {
     static constexpr int kSize = 4;
     static constexpr bool kInt = false;
     __device__ static Acc unpack(const uint32_t* w, int i) { return __uint_as_float(w[i]); }
-    __device__ static uint32_t pack_raw(In v, int) { return __float_as_uint(v); }
-    __device__ static void store(In* p, float v) { *p = v; }
 };
 struct TrF16 {
     using In = uint16_t;
@@ -105,8 +107,6 @@ struct TrF16 {
     {
         return __half2float(__ushort_as_half(uint16_t(w[i >> 1] >> (16 * (i & 1)))));
     }
-    __device__ static uint32_t pack_raw(In v, int i) { return uint32_t(v) << (16 * (i & 1)); }
-    __device__ static void store(In* p, float v) { *p = __half_as_ushort(__float2half_rn(v)); }
 };
 struct TrBF16 {
     using In = uint16_t;
@@ -116,12 +116,6 @@ struct TrBF16 {
     __device__ static Acc unpack(const uint32_t* w, int i)
     {
         return __uint_as_float(((w[i >> 1] >> (16 * (i & 1))) & 0xffffu) << 16);
-    }
-    __device__ static uint32_t pack_raw(In v, int i) { return uint32_t(v) << (16 * (i & 1)); }
-    __device__ static void store(In* p, float v)
-    {
-        const uint32_t u = __float_as_uint(v);                       // finite v
-        *p = uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);       // round to nearest even
     }
 };
 
@@ -135,50 +129,53 @@ struct Chunk {
     uint32_t w[kWords];
 };
 
-// Load this lane's chunk of one row.  `cs` is the chunk's first sample
-// (row-relative, a multiple of C); WC = W*C.
-template <class Tr, int C, int NPL>
-__device__ __forceinline__ void load_chunk(Chunk<Tr, NPL>& ch, const typename Tr::In* rowp, int cs, int WC,
-                                           int W, bool vec, bool replicate)
+constexpr int kBufDword3 = 0x00020000;         // gfx9-family raw buffer descriptor, word 3
+constexpr int kDropOffset = 0x7ffffff0;        // past every record: loads read 0, stores are dropped
+constexpr int64_t kMaxRecords = 0x7ff00000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes)
+{
+    const int n = int(bytes < kMaxRecords ? bytes : kMaxRecords);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, n, kBufDword3);
+}
+
+// Interior chunk: unchecked vector accesses of the widest granule that
+// divides the chunk (16, 8 or 4 bytes); the planner aligns chunk starts to it.
+template <class Tr, int NPL>
+__device__ __forceinline__ void load_chunk_vec(Chunk<Tr, NPL>& ch, __amdgpu_buffer_rsrc_t rs, int voff, int soff)
 {
     constexpr int kBytes = Chunk<Tr, NPL>::kBytes;
-    if (vec && cs >= 0 && cs + NPL <= WC) {
-        const char* p = reinterpret_cast<const char*>(rowp + cs);
-        if constexpr (kBytes % 16 == 0) {
+    static_assert(kBytes % 4 == 0, "chunk must be whole dwords");
+    constexpr int kGran = (kBytes % 16 == 0) ? 16 : ((kBytes % 8 == 0) ? 8 : 4);
 #pragma unroll
-            for (int k = 0; k < kBytes / 16; ++k) {
-                const uint4 v = *reinterpret_cast<const uint4*>(p + 16 * k);
-                ch.w[4 * k + 0] = v.x; ch.w[4 * k + 1] = v.y; ch.w[4 * k + 2] = v.z; ch.w[4 * k + 3] = v.w;
-            }
-        } else if constexpr (kBytes % 8 == 0) {
-#pragma unroll
-            for (int k = 0; k < kBytes / 8; ++k) {
-                const uint2 v = *reinterpret_cast<const uint2*>(p + 8 * k);
-                ch.w[2 * k + 0] = v.x; ch.w[2 * k + 1] = v.y;
-            }
-        } else if constexpr (kBytes % 4 == 0) {
-#pragma unroll
-            for (int k = 0; k < kBytes / 4; ++k) ch.w[k] = *reinterpret_cast<const uint32_t*>(p + 4 * k);
-        } else {   // 2-byte granules (uint8 with NPL = 2, 6, ...)
-#pragma unroll
-            for (int k = 0; k < Chunk<Tr, NPL>::kWords; ++k) ch.w[k] = 0;
-#pragma unroll
-            for (int k = 0; k < kBytes / 2; ++k)
-                ch.w[k >> 1] |= uint32_t(*reinterpret_cast<const uint16_t*>(p + 2 * k)) << (16 * (k & 1));
+    for (int k = 0; k < kBytes / kGran; ++k) {
+        if constexpr (kGran == 16) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16 * k, soff, 0);
+            ch.w[4 * k + 0] = v[0]; ch.w[4 * k + 1] = v[1]; ch.w[4 * k + 2] = v[2]; ch.w[4 * k + 3] = v[3];
+        } else if constexpr (kGran == 8) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 8 * k, soff, 0);
+            ch.w[2 * k + 0] = v[0]; ch.w[2 * k + 1] = v[1];
+        } else {
+            ch.w[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 4 * k, soff, 0);
         }
-        return;
     }
-    // border or unaligned rows: one element at a time, extended per boundary
+}
+
+// Border chunk: element by element at precomputed offsets (clamped for
+// REPLICATE, kDropOffset -> 0 for ZERO).
+template <class Tr, int NPL>
+__device__ __forceinline__ void load_chunk_elem(Chunk<Tr, NPL>& ch, __amdgpu_buffer_rsrc_t rs, const int* eoff,
+                                                int soff)
+{
 #pragma unroll
     for (int k = 0; k < Chunk<Tr, NPL>::kWords; ++k) ch.w[k] = 0;
-    const int x0 = floor_div(cs, C);
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-        int x = x0 + i / C;
-        const int c = i % C;
-        bool inside = (x >= 0 && x < W);
-        if (!inside && replicate) { x = x < 0 ? 0 : W - 1; inside = true; }
-        if (inside) ch.w[(i * Tr::kSize) / 4] |= Tr::pack_raw(rowp[x * C + c], i);
+        uint32_t raw;
+        if constexpr (Tr::kSize == 1) raw = __builtin_amdgcn_raw_buffer_load_b8(rs, eoff[i], soff, 0);
+        else if constexpr (Tr::kSize == 2) raw = __builtin_amdgcn_raw_buffer_load_b16(rs, eoff[i], soff, 0);
+        else raw = __builtin_amdgcn_raw_buffer_load_b32(rs, eoff[i], soff, 0);
+        ch.w[(i * Tr::kSize) / 4] |= raw << (8 * ((i * Tr::kSize) % 4));
     }
 }
 
@@ -194,203 +191,268 @@ __device__ __forceinline__ uint32_t exact_round_div(uint64_t U, const ImgParams&
     return q;
 }
 
-// Rows per group: keep two groups of raw chunks within ~64 VGPRs.
-template <int NPL, int SIZE>
-struct GroupRows {
-    static constexpr int kWords = (NPL * SIZE + 3) / 4;
-    static constexpr int value = kWords <= 4 ? 8 : (kWords <= 8 ? 4 : 2);
+// Orders this wave's LDS writes before its later reads (one-wave groups).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class Tr>
+__device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v);
+template <>
+__device__ __forceinline__ void store_out<TrF32>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void store_out<TrF16>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), rs, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void store_out<TrBF16>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
+{
+    const uint32_t u = __float_as_uint(v);                          // finite v
+    __builtin_amdgcn_raw_buffer_store_b16(uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16), rs, voff, soff, 0);
+}
+
+// Per-task constants.
+struct TaskGeom {
+    int s0, y0, hs, a0, off, niter, ybase;
 };
 
 // --------------------------------------------------------------------------
-// One task: 64 sample-columns x hs output rows.
+// The streaming loop of one task.  The column ring keeps L = roundup(2R + 1
+// + G, G) rows of running column sums plus G mirror rows (slots 0..G-1 are
+// also written at L..L+G-1), so the taps of a whole group are read at
+// (per-group base) + (row * 256 bytes) without any per-row modulo.
 // --------------------------------------------------------------------------
-template <class Tr, int C, int NPL, int KT>
-__device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t* lds)
+template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE>
+__device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
 {
-    using In = typename Tr::In;
     using Acc = typename Tr::Acc;
     constexpr bool kInt = Tr::kInt;
-    constexpr int G = GroupRows<NPL, Tr::kSize>::value;
-    constexpr int PW = kWave * NPL;           // LDS width of one running-sum row
+    constexpr int G = kWave / SEG;             // rows per group
+    constexpr int PW = SEG * NPL;              // span capacity = LDS row width
+    constexpr int PF = 3;                      // groups of loads in flight
+    constexpr int es = Tr::kSize;
     const int lane = threadIdx.x;
-    const int WC = ip.W * C;
-    const int strip = task % ip.nstrips;
-    const int seg = task / ip.nstrips;
-    const int s0 = strip * kWave;
-    const int y0 = seg * ip.hs;
-    const int hs = min(ip.hs, ip.H - y0);
+    const int jrow = lane / SEG;               // row pass: row within the group
+    const int q = lane % SEG;                  // row pass: chunk within the row
     const int R = ip.R;
     const int L = ip.L;
     const int H = ip.H;
+    const int W = ip.W;
+    const int WC = W * C;
     const bool replicate = (ip.boundary == RSG_REPLICATE);
-    const bool vec = ip.vec != 0;
 
-    const int a0 = floor_div(s0 - (R + 1) * C, ip.align) * ip.align;
-    const int off = s0 - a0;                  // span index of this strip's first sample
-    const int cs = a0 + NPL * lane;           // this lane's chunk
+    Acc* P = reinterpret_cast<Acc*>(lds);      // G rows x PW running sums
+    Acc* ring = P + G * PW;                    // (L + G) rows x 64 column sums
 
-    Acc* P = reinterpret_cast<Acc*>(lds);     // G rows x PW
-    Acc* ring = P + G * PW;                   // L rows x 64
+    // ---- source / destination descriptors (task-relative row offsets) ----
+    const int y_lo = max(0, tg.ybase);        // loads clamp rows into [y_lo, H - 1]
+    const int y_hi = H - 1;
+    const int64_t sstride = ip.src_stride * es;
+    const int64_t dstride = ip.dst_stride * es;
+    const char* sbase = reinterpret_cast<const char*>(ip.src) + int64_t(y_lo) * sstride;
+    const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(y_hi - y_lo) * sstride + int64_t(WC) * es);
+    const char* dbase = reinterpret_cast<const char*>(ip.dst) + int64_t(tg.y0) * dstride;
+    const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(dbase, int64_t(tg.hs - 1) * dstride + int64_t(WC) * es);
+    const int s = tg.s0 + lane;                // this lane's column
+    const int out_voff = (s < WC) ? s * es : kDropOffset;
 
-    int tp[KT], tm[KT];                       // LDS indices of the box ends
+    // ---- row-pass chunk offsets ----
+    // Each row segment loads a different input row, so the row offset is a
+    // per-lane (VGPR) part of the buffer offset; the descriptor and soffset
+    // stay uniform.
+    const int cs = tg.a0 + NPL * q;            // first span sample of this lane's chunk
+    const int vec_voff = cs * es;
+    int eoff[EDGE ? NPL : 1];
+    if constexpr (EDGE) {
+        const int x0 = floor_div(cs, C);
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int x = x0 + i / C;
+            const int xc = x < 0 ? 0 : (x >= W ? W - 1 : x);
+            eoff[i] = (replicate || (x >= 0 && x < W)) ? (xc * C + i % C) * es : -1;   // -1: zero sample
+        }
+    }
+    const int sstride32 = int(sstride);
+    auto load = [&](Chunk<Tr, NPL>& ch, int g) {
+        int y = tg.ybase + g * G + jrow;       // clamped: rows past the task end are re-read, unused
+        y = y < 0 ? 0 : (y >= H ? H - 1 : y);
+        const int rowoff = (y - y_lo) * sstride32;
+        if constexpr (EDGE) {
+            int vo[NPL];
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) vo[i] = eoff[i] < 0 ? kDropOffset : eoff[i] + rowoff;
+            load_chunk_elem<Tr, NPL>(ch, rs_src, vo, 0);
+        } else {
+            load_chunk_vec<Tr, NPL>(ch, rs_src, vec_voff + rowoff, 0);
+        }
+    };
+
+    // ---- combine taps ----
+    int tp[KT], tm[KT];                        // LDS indices of the row box ends
     float wf[KT];
     uint32_t wm[KT];
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
-        tp[k] = off + lane + ip.r[k] * C;
-        tm[k] = off + lane - (ip.r[k] + 1) * C;
+        tp[k] = tg.off + lane + ip.r[k] * C;
+        tm[k] = tg.off + lane - (ip.r[k] + 1) * C;
         wf[k] = ip.wf[k];
         wm[k] = ip.m[k];
     }
     const float dc = ip.dc32;
+    const int seg_lead = lane & ~(SEG - 1);    // first lane of this lane's row segment
 
-    const In* src = reinterpret_cast<const In*>(ip.src);
-    In* dst = reinterpret_cast<In*>(ip.dst);
-    const int s = s0 + lane;                  // this lane's column
-    const bool s_ok = s < WC;
+    const int ngroups = (tg.niter + G - 1) / G;
+    const int ngroups_pf = (ngroups + PF - 1) / PF * PF;
 
-    const int niter = 2 * R + 1 + hs;
-    const int ngroups = (niter + G - 1) / G;
-    const int ybase = y0 - R - 1;
-
-    auto load_group = [&](Chunk<Tr, NPL>* buf, int g) {
+    Chunk<Tr, NPL> buf[PF];
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            const int it = g * G + j;
-            if (it < niter) {
-                int y = ybase + it;
-                const bool inside = (y >= 0 && y < H);
-                if (inside || replicate) {
-                    y = y < 0 ? 0 : (y >= H ? H - 1 : y);
-                    load_chunk<Tr, C, NPL>(buf[j], src + int64_t(y) * ip.src_stride, cs, WC, ip.W, vec, replicate);
-                }
-            }
-        }
-    };
-
-    Chunk<Tr, NPL> nxt[G];
-    load_group(nxt, 0);
+    for (int b = 0; b < PF; ++b) load(buf[b], b);
 
     Acc colacc = Acc(0);
-    float c2 = 0.0f;                          // column offset (float types)
-    int slot0 = 0;                            // ring slot of the group's first row
+    float c2 = 0.0f;                           // column offset (float types)
+    int slot0 = 0;                             // ring slot of the group's first row
 
-    for (int g = 0; g < ngroups; ++g) {
-        Chunk<Tr, NPL> cur[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j) cur[j] = nxt[j];
-        if (g + 1 < ngroups) load_group(nxt, g + 1);
+    auto group = [&](int g, Chunk<Tr, NPL>& bf) {
+        const Chunk<Tr, NPL> cur = bf;
+        load(bf, g + PF);
         const int it0 = g * G;
 
-        // ---- row running sums of the group (Eq. alg1) ----
-        float rowoff[G];
+        // ---- running sum of this lane's row over its span (Eq. alg1) ----
+        Acc v[NPL];
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            rowoff[j] = 0.0f;
-            const int it = it0 + j;
-            const int y = ybase + it;
-            const bool live = (it < niter) && (replicate || (y >= 0 && y < H));
-            if (live) {
-                Acc v[NPL];
+        for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(cur.w, i);
+        float myoff = 0.0f;
+        if constexpr (!kInt) {
+            // offset: the first span sample of this row (added back via the DC gain)
+            myoff = __shfl(v[0], seg_lead);
 #pragma unroll
-                for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(cur[j].w, i);
-                if constexpr (!kInt) {
-                    // offset: the span sample held first by the lane at the strip start
-                    const float c = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v[0]), off / NPL));
-                    rowoff[j] = c;
+            for (int i = 0; i < NPL; ++i) v[i] -= myoff;
+        }
 #pragma unroll
-                    for (int i = 0; i < NPL; ++i) v[i] -= c;
-                }
+        for (int i = C; i < NPL; ++i) v[i] = v[i] + v[i - C];
 #pragma unroll
-                for (int i = C; i < NPL; ++i) v[i] = v[i] + v[i - C];
+        for (int c = 0; c < C; ++c) {
+            const Acc tot = v[NPL - C + c];
+            const Acc ex = segment_inclusive_scan<SEG>(tot) - tot;     // exclusive within the segment
 #pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const Acc ex = wave_exclusive_scan<Acc>(v[NPL - C + c]);
+            for (int i = c; i < NPL; i += C) v[i] = v[i] + ex;
+        }
+        {   // 16-byte stores (NPL is a multiple of 4)
+            using Acc4 = typename std::conditional<kInt, uint4, float4>::type;
+            Acc4* dst4 = reinterpret_cast<Acc4*>(P + jrow * PW + q * NPL);
 #pragma unroll
-                    for (int i = c; i < NPL; i += C) v[i] = v[i] + ex;
-                }
-#pragma unroll
-                for (int i = 0; i < NPL; ++i) P[j * PW + lane * NPL + i] = v[i];
+            for (int h = 0; h < NPL / 4; ++h) {
+                Acc4 t4;
+                t4.x = v[4 * h + 0]; t4.y = v[4 * h + 1]; t4.z = v[4 * h + 2]; t4.w = v[4 * h + 3];
+                dst4[h] = t4;
             }
         }
-        __syncthreads();
+        wave_lds_fence();
 
-        // ---- box differences along the row (Eq. indep) ----
+        // ---- box differences along the rows (Eq. indep); lane = column ----
         Acc T[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            const int it = it0 + j;
-            const int y = ybase + it;
-            const bool live = (it < niter) && (replicate || (y >= 0 && y < H));
-            Acc t = Acc(0);
-            if (live) {
-                const Acc* Pj = P + j * PW;
-                if constexpr (kInt) {
+            const Acc* Pj = P + j * PW;
+            Acc t;
+            if constexpr (kInt) {
+                t = 0;
 #pragma unroll
-                    for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
-                } else {
-                    t = rowoff[j] * dc;
+                for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
+            } else {
+                const float cj = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(myoff), j * SEG));
+                t = cj * dc;
 #pragma unroll
-                    for (int k = 0; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
-                }
+                for (int k = 0; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
+            }
+            if (!replicate) {
+                const int y = tg.ybase + it0 + j;
+                if (y < 0 || y >= H) t = Acc(0);
             }
             T[j] = t;
         }
-
-        // ---- running sums down the columns, into the ring (Eq. alg1) ----
-#pragma unroll
-        for (int j = 0; j < G; ++j) {
-            const int it = it0 + j;
-            if (it < niter) {
-                if constexpr (kInt) {
-                    colacc += T[j];
-                } else {
-                    if (it == 0) c2 = T[j];
-                    colacc += T[j] - c2;
-                }
-                int sl = slot0 + j;
-                sl -= (sl >= L) ? L : 0;
-                ring[sl * kWave + lane] = colacc;
-            }
+        if constexpr (!kInt) {
+            if (g == 0) c2 = T[0];
         }
 
-        // ---- box differences down the columns, for row y - R (Eq. indep) ----
+        // ---- running sums down the columns into the ring (Eq. alg1) ----
+        const int wbase = slot0 * kWave + lane;
+        const int mbase = (slot0 == 0 ? L : slot0) * kWave + lane;
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if constexpr (kInt) colacc += T[j];
+            else colacc += T[j] - c2;
+            ring[wbase + j * kWave] = colacc;
+            ring[mbase + j * kWave] = colacc;       // mirror copy (same slot unless slot0 == 0)
+        }
+        wave_lds_fence();
+
+        // ---- box differences down the columns for rows it - R (Eq. indep) ----
+        int bp[KT], bm[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            int a = slot0 - R + ip.r[k];
+            int b = slot0 - R - ip.r[k] - 1;
+            a += (a < 0) ? L : 0;
+            b += (b < 0) ? L : 0;
+            bp[k] = a * kWave + lane;
+            bm[k] = b * kWave + lane;
+        }
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             const int it = it0 + j;
-            if (it < niter && it >= 2 * R + 1) {
-                int sl = slot0 + j;
-                sl -= (sl >= L) ? L : 0;
-                const int yo = ybase + it - R;
-                In* orow = dst + int64_t(yo) * ip.dst_stride;
-                if constexpr (kInt) {
-                    uint64_t U = 0;
+            const bool emit = (it >= 2 * R + 1) && (it < tg.niter);
+            const int soff = emit ? int(int64_t(it - 2 * R - 1) * dstride) : 0;   // row y0 + it - 2R - 1
+            const int voff = emit ? out_voff : kDropOffset;
+            if constexpr (kInt) {
+                uint64_t U = 0;
 #pragma unroll
-                    for (int k = 0; k < KT; ++k) {
-                        int a = sl - R + ip.r[k];
-                        int b = sl - R - ip.r[k] - 1;
-                        a += (a < 0) ? L : 0;
-                        b += (b < 0) ? L : 0;
-                        U += uint64_t(wm[k]) * uint32_t(ring[a * kWave + lane] - ring[b * kWave + lane]);
-                    }
-                    if (s_ok) orow[s] = In(exact_round_div(U, ip));
-                } else {
-                    float o = c2 * dc;
+                for (int k = 0; k < KT; ++k)
+                    U += uint64_t(wm[k]) * uint32_t(ring[bp[k] + j * kWave] - ring[bm[k] + j * kWave]);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, voff, soff, 0);
+            } else {
+                float o = c2 * dc;
 #pragma unroll
-                    for (int k = 0; k < KT; ++k) {
-                        int a = sl - R + ip.r[k];
-                        int b = sl - R - ip.r[k] - 1;
-                        a += (a < 0) ? L : 0;
-                        b += (b < 0) ? L : 0;
-                        o = fmaf(wf[k], ring[a * kWave + lane] - ring[b * kWave + lane], o);
-                    }
-                    if (s_ok) Tr::store(orow + s, o);
-                }
+                for (int k = 0; k < KT; ++k) o = fmaf(wf[k], ring[bp[k] + j * kWave] - ring[bm[k] + j * kWave], o);
+                store_out<Tr>(rs_dst, voff, soff, o);
             }
         }
         slot0 += G;
         slot0 -= (slot0 >= L) ? L : 0;
+    };
+
+    for (int g = 0; g < ngroups_pf; g += PF) {
+        group(g, buf[0]);
+        group(g + 1, buf[1]);
+        group(g + 2, buf[2]);
     }
+}
+
+// One task: 64 sample-columns x hs output rows of image `ip`.
+template <class Tr, int C, int SEG, int NPL, int KT>
+__device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t* lds)
+{
+    TaskGeom tg;
+    const int strip = task % ip.nstrips;
+    const int seg = task / ip.nstrips;
+    tg.s0 = strip * kWave;
+    tg.y0 = seg * ip.hs;
+    tg.hs = min(ip.hs, ip.H - tg.y0);
+    tg.a0 = floor_div(tg.s0 - (ip.R + 1) * C, ip.align) * ip.align;
+    tg.off = tg.s0 - tg.a0;
+    tg.niter = 2 * ip.R + 1 + tg.hs;
+    tg.ybase = tg.y0 - ip.R - 1;
+    const int WC = ip.W * C;
+    const bool interior = ip.vec && tg.a0 >= 0 && tg.a0 + SEG * NPL <= WC;
+    if (interior) stream_task<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
+    else stream_task<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
 }
 
 // Task order: blocks are dealt to the 8 XCDs round-robin; give each XCD a
@@ -405,16 +467,17 @@ __device__ __forceinline__ int xcd_task(int b, int n)
     return x * q + min(x, rem) + i;
 }
 
-template <class Tr, int C, int NPL, int KT>
+template <class Tr, int C, int SEG, int NPL, int KT>
 __global__ __launch_bounds__(64) void k_single(ImgParams ip)
 {
     extern __shared__ uint32_t lds[];
-    run_task<Tr, C, NPL, KT>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
+    run_task<Tr, C, SEG, NPL, KT>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
 }
 
 // Persistent batch kernel for one (dtype, C, K) class: each wave pops
 // (image, task) items off a shared counter until the list is exhausted.
-template <class Tr, int C, int KT, int N0, int N1, int N2, int N3>
+// The image's scan layout (SEG, NPL) selects among four instantiations.
+template <class Tr, int C, int KT, int S0, int N0, int S1, int N1, int S2, int N2, int S3, int N3>
 __global__ __launch_bounds__(64) void k_batch(const ImgParams* __restrict__ imgs,
                                               const BatchTask* __restrict__ tasks, int ntasks,
                                               unsigned* __restrict__ counter)
@@ -427,11 +490,10 @@ __global__ __launch_bounds__(64) void k_batch(const ImgParams* __restrict__ imgs
         if (t >= unsigned(ntasks)) break;
         const BatchTask bt = tasks[t];
         const ImgParams& ip = imgs[bt.img];
-        const int npl = ip.npl;
-        if (npl == N0) run_task<Tr, C, N0, KT>(ip, bt.task, lds);
-        else if (N1 && npl == N1) run_task<Tr, C, (N1 ? N1 : N0), KT>(ip, bt.task, lds);
-        else if (N2 && npl == N2) run_task<Tr, C, (N2 ? N2 : N0), KT>(ip, bt.task, lds);
-        else if (N3 && npl == N3) run_task<Tr, C, (N3 ? N3 : N0), KT>(ip, bt.task, lds);
+        if (ip.seg == S0 && ip.npl == N0) run_task<Tr, C, S0, N0, KT>(ip, bt.task, lds);
+        else if (ip.seg == S1 && ip.npl == N1) run_task<Tr, C, S1, N1, KT>(ip, bt.task, lds);
+        else if (ip.seg == S2 && ip.npl == N2) run_task<Tr, C, S2, N2, KT>(ip, bt.task, lds);
+        else if (ip.seg == S3 && ip.npl == N3) run_task<Tr, C, S3, N3, KT>(ip, bt.task, lds);
         __syncthreads();
     }
 }

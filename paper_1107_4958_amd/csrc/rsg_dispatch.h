@@ -9,13 +9,11 @@
 namespace rsg {
 namespace dispatch {
 
-// Scan-chunk options (samples per lane, multiples of C) per channel count;
-// the planner draws from the same lists.
-template <int C> struct Npls;
-template <> struct Npls<1> { static constexpr int v[4] = {2, 4, 8, 16}; };
-template <> struct Npls<2> { static constexpr int v[4] = {4, 8, 16, 0}; };
-template <> struct Npls<3> { static constexpr int v[4] = {6, 12, 24, 0}; };
-template <> struct Npls<4> { static constexpr int v[4] = {4, 8, 16, 0}; };
+// Row-scan layouts per channel count, matching scan_layout().
+template <int C> struct Layouts {
+    static constexpr int S[4] = {16, 32, 64, 64};
+    static constexpr int N[4] = {C == 3 ? 12 : 8, C == 3 ? 12 : 8, C == 3 ? 12 : 8, C == 3 ? 24 : 16};
+};
 
 inline int set_lds_limit(const void* fn, uint32_t bytes)
 {
@@ -25,37 +23,36 @@ inline int set_lds_limit(const void* fn, uint32_t bytes)
     return RSG_OK;
 }
 
-template <class Tr, int C, int NPL, int KT>
+template <class Tr, int C, int SEG, int NPL, int KT>
 int launch_one(const ImgParams& ip, hipStream_t st)
 {
-    auto fn = dev::k_single<Tr, C, NPL, KT>;
+    auto fn = dev::k_single<Tr, C, SEG, NPL, KT>;
     int rc = set_lds_limit(reinterpret_cast<const void*>(fn), ip.lds_bytes);
     if (rc != RSG_OK) return rc;
     hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3(kWave), ip.lds_bytes, st, ip);
     return RSG_OK;
 }
 
-template <class Tr, int C, int NPL>
+template <class Tr, int C, int SEG, int NPL>
 int launch_k(const ImgParams& ip, hipStream_t st)
 {
     switch (ip.kt) {
-    case 3: return launch_one<Tr, C, NPL, 3>(ip, st);
-    case 4: return launch_one<Tr, C, NPL, 4>(ip, st);
-    case 5: return launch_one<Tr, C, NPL, 5>(ip, st);
+    case 3: return launch_one<Tr, C, SEG, NPL, 3>(ip, st);
+    case 4: return launch_one<Tr, C, SEG, NPL, 4>(ip, st);
+    case 5: return launch_one<Tr, C, SEG, NPL, 5>(ip, st);
     default: return set_error(RSG_EUNSUPPORTED, "no kernel for %d taps", ip.kt);
     }
 }
 
 template <class Tr, int C>
-int launch_npl(const ImgParams& ip, hipStream_t st)
+int launch_layout(const ImgParams& ip, hipStream_t st)
 {
-    constexpr int n0 = Npls<C>::v[0], n1 = Npls<C>::v[1], n2 = Npls<C>::v[2], n3 = Npls<C>::v[3];
-    if (ip.npl == n0) return launch_k<Tr, C, n0>(ip, st);
-    if (ip.npl == n1) return launch_k<Tr, C, n1>(ip, st);
-    if (ip.npl == n2) return launch_k<Tr, C, n2>(ip, st);
-    if constexpr (n3 != 0)
-        if (ip.npl == n3) return launch_k<Tr, C, n3>(ip, st);
-    return set_error(RSG_EUNSUPPORTED, "no kernel for C=%d npl=%d", C, ip.npl);
+    using Lo = Layouts<C>;
+    if (ip.seg == Lo::S[0] && ip.npl == Lo::N[0]) return launch_k<Tr, C, Lo::S[0], Lo::N[0]>(ip, st);
+    if (ip.seg == Lo::S[1] && ip.npl == Lo::N[1]) return launch_k<Tr, C, Lo::S[1], Lo::N[1]>(ip, st);
+    if (ip.seg == Lo::S[2] && ip.npl == Lo::N[2]) return launch_k<Tr, C, Lo::S[2], Lo::N[2]>(ip, st);
+    if (ip.seg == Lo::S[3] && ip.npl == Lo::N[3]) return launch_k<Tr, C, Lo::S[3], Lo::N[3]>(ip, st);
+    return set_error(RSG_EUNSUPPORTED, "no kernel for C=%d seg=%d npl=%d", C, ip.seg, ip.npl);
 }
 
 template <class Tr>
@@ -63,10 +60,10 @@ int launch_single_t(const ImgParams& ip, hipStream_t st)
 {
     int rc;
     switch (ip.C) {
-    case 1: rc = launch_npl<Tr, 1>(ip, st); break;
-    case 2: rc = launch_npl<Tr, 2>(ip, st); break;
-    case 3: rc = launch_npl<Tr, 3>(ip, st); break;
-    case 4: rc = launch_npl<Tr, 4>(ip, st); break;
+    case 1: rc = launch_layout<Tr, 1>(ip, st); break;
+    case 2: rc = launch_layout<Tr, 2>(ip, st); break;
+    case 3: rc = launch_layout<Tr, 3>(ip, st); break;
+    case 4: rc = launch_layout<Tr, 4>(ip, st); break;
     default: return set_error(RSG_EINVAL, "bad channel count %d", ip.C);
     }
     if (rc != RSG_OK) return rc;
@@ -78,8 +75,8 @@ int launch_single_t(const ImgParams& ip, hipStream_t st)
 template <class Tr, int C, int KT>
 int batch_one(const BatchClassLaunch& b, hipStream_t st)
 {
-    constexpr int n0 = Npls<C>::v[0], n1 = Npls<C>::v[1], n2 = Npls<C>::v[2], n3 = Npls<C>::v[3];
-    auto fn = dev::k_batch<Tr, C, KT, n0, n1, n2, n3>;
+    using Lo = Layouts<C>;
+    auto fn = dev::k_batch<Tr, C, KT, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2], Lo::N[2], Lo::S[3], Lo::N[3]>;
     int rc = set_lds_limit(reinterpret_cast<const void*>(fn), b.lds);
     if (rc != RSG_OK) return rc;
     hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks, b.d_counter);

@@ -41,10 +41,11 @@ struct ImgParams {
     float invG2;                   // 1 / G^2 rounded to FP32 (quotient estimate)
     int32_t R;                     // max r
     // tile plan
+    int32_t seg;                   // lanes per row in the row scan (16, 32, 64)
     int32_t npl;                   // samples per lane in the row scan
-    int32_t G;                     // input rows per group (function of dtype and npl)
+    int32_t G;                     // input rows per group = 64 / seg
     int32_t hs;                    // output rows per task
-    int32_t L;                     // column ring length = 2R + 1 + G
+    int32_t L;                     // column ring length: roundup(2R + 1 + G, G) (+ G mirror rows)
     int32_t align;                 // span start alignment (samples)
     int32_t vec;                   // 1: rows allow vector loads of one chunk
     int32_t nstrips, nsegs, ntasks;
@@ -82,12 +83,16 @@ int launch_batch_class_u8(const BatchClassLaunch& b, hipStream_t stream);
 int launch_batch_class_f32(const BatchClassLaunch& b, hipStream_t stream);
 int launch_batch_class_f16(const BatchClassLaunch& b, hipStream_t stream);
 int launch_batch_class_bf16(const BatchClassLaunch& b, hipStream_t stream);
-// Rows per group of the kernel for (dtype, npl): two groups of raw chunks
-// stay within ~64 VGPRs.
-inline int group_rows(int dt, int npl)
+// Row-scan layouts (lanes per row, samples per lane) instantiated per
+// channel count, in the order the planner tries them.
+constexpr int kLayouts = 4;
+inline void scan_layout(int C, int i, int* seg, int* npl)
 {
-    const int words = (npl * (dt == RSG_U8 ? 1 : (dt == RSG_F32 ? 4 : 2)) + 3) / 4;
-    return words <= 4 ? 8 : (words <= 8 ? 4 : 2);
+    static const int segs[kLayouts] = {16, 32, 64, 64};
+    static const int n1[kLayouts] = {8, 8, 8, 16};      // C = 1, 2, 4
+    static const int n3[kLayouts] = {12, 12, 12, 24};   // C = 3
+    *seg = segs[i];
+    *npl = (C == 3) ? n3[i] : n1[i];
 }
 // h_stage: optional pinned host buffer of >= batch_workspace_bytes() used to
 // stage the work list (must not be reused before the copy has executed);

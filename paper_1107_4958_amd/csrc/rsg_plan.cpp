@@ -29,19 +29,6 @@ constexpr uint32_t kLdsLimit = 160u * 1024u;    // gfx950: 160 KiB of LDS per CU
 int gcd_i(int a, int b) { while (b) { int t = a % b; a = b; b = t; } return a; }
 int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
 
-// scan-chunk options per channel count (samples per lane, multiples of C);
-// the kernel dispatch instantiates exactly these
-const int* npl_options(int C, int* n)
-{
-    static const int c1[] = {2, 4, 8, 16}, c2[] = {4, 8, 16}, c3[] = {6, 12, 24}, c4[] = {4, 8, 16};
-    switch (C) {
-    case 1: *n = 4; return c1;
-    case 2: *n = 3; return c2;
-    case 3: *n = 3; return c3;
-    default: *n = 3; return c4;
-    }
-}
-
 // Tuning table (text): lines "dtype C rlo rhi hs", '#' starts a comment.
 // The segment height of an image whose largest half-width R lies in
 // [rlo, rhi] is taken from the first matching line.
@@ -106,6 +93,8 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     const int64_t ss = d.src_stride ? d.src_stride : WC;
     const int64_t ds = d.dst_stride ? d.dst_stride : WC;
     if (ss < WC || ds < WC) return set_error(RSG_EINVAL, "row stride smaller than W*C");
+    if ((ss > ds ? ss : ds) * 8 > (int64_t(1) << 30) / 1024)
+        return set_error(RSG_EUNSUPPORTED, "row stride too large (%lld elements)", (long long)(ss > ds ? ss : ds));
     const int es = dtype_size(d.dt);
     {   // source and destination must not overlap
         const char* s0 = static_cast<const char*>(d.src);
@@ -156,21 +145,26 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         p.dc32 = float(dc);
     }
 
-    // ---- scan chunk: smallest option whose 64 lanes cover the row span ----
+    // ---- row-scan layout: first (lanes per row, samples per lane) whose
+    //      segment covers the row span [s0 - (R+1)C, s0 + 64 + RC) ----
     const int C = d.C;
-    int nopt = 0;
-    const int* opts = npl_options(C, &nopt);
-    int npl = 0, align = 1;
-    for (int i = 0; i < nopt; ++i) {
-        const int cb = opts[i] * es;                 // chunk bytes
+    int seg = 0, npl = 0, align = 1;
+    for (int i = 0; i < kLayouts && !seg; ++i) {
+        int sg, n;
+        scan_layout(C, i, &sg, &n);
+        const int cb = n * es;                       // chunk bytes
         const int unit = gcd_i(cb, 16);              // vector load granule
         const int al = lcm_i(C, std::max(1, unit / es));
         const int64_t span = int64_t(kWave) + int64_t(2 * R + 1) * C + al - 1;
-        if (span <= int64_t(kWave) * opts[i]) { npl = opts[i]; align = al; break; }
+        if (span <= int64_t(sg) * n) { seg = sg; npl = n; align = al; }
     }
-    if (!npl)
+    if (!seg) {
+        int sg, n;
+        scan_layout(C, kLayouts - 1, &sg, &n);
         return set_error(RSG_EUNSUPPORTED, "box half-width %d too wide for C=%d (largest row span %d samples)",
-                         R, C, kWave * opts[nopt - 1]);
+                         R, C, sg * n);
+    }
+    p.seg = seg;
     p.npl = npl;
     p.align = align;
     {
@@ -178,9 +172,9 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         const uintptr_t sa = reinterpret_cast<uintptr_t>(d.src);
         p.vec = (sa % unit == 0) && ((ss * es) % unit == 0);
     }
-    p.G = group_rows(d.dt, npl);
-    p.L = 2 * R + 1 + p.G;
-    p.lds_bytes = uint32_t(4 * (p.G * kWave * npl + p.L * kWave));
+    p.G = kWave / seg;
+    p.L = (2 * R + 1 + p.G + p.G - 1) / p.G * p.G;
+    p.lds_bytes = uint32_t(4 * (p.G * seg * npl + (p.L + p.G) * kWave));
     if (p.lds_bytes > kLdsLimit)
         return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", p.lds_bytes, kLdsLimit);
     p.nstrips = int((WC + kWave - 1) / kWave);
