@@ -311,30 +311,49 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     const int ngroups = (tg.niter + G - 1) / G;
     const int ngroups_pf = (ngroups + PF - 1) / PF * PF;
 
+    // Prologue: the first PF groups' loads, in order, each followed by G
+    // dropped stores, so the memory-operation sequence before the loop
+    // matches the one around its back edge and the loop's waits stay exact.
     Chunk<Tr, NPL> buf[PF];
 #pragma unroll
-    for (int b = 0; b < PF; ++b) load(buf[b], b);
+    for (int b = 0; b < PF; ++b) {
+        __builtin_amdgcn_sched_barrier(0);
+        load(buf[b], b);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {         // distinct offsets: not merged by the compiler
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (b * G + j), 0, 0);
+            else store_out<Tr>(rs_dst, kDropOffset - 64 * (b * G + j), 0, 0.0f);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
 
     Acc colacc = Acc(0);
     float c2 = 0.0f;                           // column offset (float types)
     int slot0 = 0;                             // ring slot of the group's first row
 
     auto group = [&](int g, Chunk<Tr, NPL>& bf) {
-        const Chunk<Tr, NPL> cur = bf;
-        load(bf, g + PF);
-        const int it0 = g * G;
-
-        // ---- running sum of this lane's row over its span (Eq. alg1) ----
+        // Consume this group's chunk, then reuse its registers for the load
+        // of group g + PF, so the loop-carried buffers are written in place
+        // and the wait for a load comes PF groups after it was issued.
+        __builtin_amdgcn_sched_barrier(0);
         Acc v[NPL];
-#pragma unroll
-        for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(cur.w, i);
         float myoff = 0.0f;
         if constexpr (!kInt) {
             // offset: the first span sample of this row (added back via the DC gain)
-            myoff = __shfl(v[0], seg_lead);
+            myoff = __shfl(Tr::unpack(bf.w, 0), seg_lead);
 #pragma unroll
-            for (int i = 0; i < NPL; ++i) v[i] -= myoff;
+            for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(bf.w, i) - myoff;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(bf.w, i);
         }
+        __builtin_amdgcn_sched_barrier(0);
+        load(bf, g + PF);
+        __builtin_amdgcn_sched_barrier(0);
+        const int it0 = g * G;
+
+        // ---- running sum of this lane's row over its span (Eq. alg1) ----
 #pragma unroll
         for (int i = C; i < NPL; ++i) v[i] = v[i] + v[i - C];
 #pragma unroll
