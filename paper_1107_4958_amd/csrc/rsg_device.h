@@ -53,22 +53,26 @@ constexpr int kDppRowShr4 = 0x114;
 constexpr int kDppRowShr8 = 0x118;
 constexpr int kDppRowBcast15 = 0x142;
 constexpr int kDppRowBcast31 = 0x143;
+constexpr int kDppRowNewBcast7 = 0x157;     // gfx90a+: every lane of a 16-lane row reads lane 7 of it
 
-template <int CTRL, int ROWMASK>
+// Lanes in rows / banks masked off receive 0.
+template <int CTRL, int ROWMASK, int BANKMASK = 0xf>
 __device__ __forceinline__ uint32_t dpp(uint32_t v)
 {
-    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWMASK, 0xf, true));
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWMASK, BANKMASK, true));
 }
 
 __device__ __forceinline__ uint32_t addv(uint32_t a, uint32_t b) { return a + b; }
 __device__ __forceinline__ float addv(float a, float b) { return a + b; }
+__device__ __forceinline__ uint32_t subv(uint32_t a, uint32_t b) { return a - b; }
+__device__ __forceinline__ float subv(float a, float b) { return a - b; }
 __device__ __forceinline__ uint32_t bits(uint32_t v) { return v; }
 __device__ __forceinline__ uint32_t bits(float v) { return __float_as_uint(v); }
 template <class T> __device__ __forceinline__ T frombits(uint32_t v);
 template <> __device__ __forceinline__ uint32_t frombits<uint32_t>(uint32_t v) { return v; }
 template <> __device__ __forceinline__ float frombits<float>(uint32_t v) { return __uint_as_float(v); }
 
-// Inclusive scan across segments of SEG lanes (16, 32 or 64).
+// Inclusive scan across segments of SEG lanes (8, 16, 32 or 64).
 template <int SEG, class T>
 __device__ __forceinline__ T segment_inclusive_scan(T x)
 {
@@ -76,6 +80,8 @@ __device__ __forceinline__ T segment_inclusive_scan(T x)
     x = addv(x, frombits<T>(dpp<kDppRowShr2, 0xf>(bits(x))));
     x = addv(x, frombits<T>(dpp<kDppRowShr4, 0xf>(bits(x))));
     x = addv(x, frombits<T>(dpp<kDppRowShr8, 0xf>(bits(x))));
+    // 8-lane segments: lanes 8..15 of each row drop the total of lanes 0..7 (banks 2 and 3 only)
+    if constexpr (SEG == 8) x = subv(x, frombits<T>(dpp<kDppRowNewBcast7, 0xf, 0xc>(bits(x))));
     if constexpr (SEG >= 32) x = addv(x, frombits<T>(dpp<kDppRowBcast15, 0xa>(bits(x))));
     if constexpr (SEG >= 64) x = addv(x, frombits<T>(dpp<kDppRowBcast31, 0xc>(bits(x))));
     return x;
@@ -130,8 +136,12 @@ struct Chunk {
 };
 
 constexpr int kBufDword3 = 0x00020000;         // gfx9-family raw buffer descriptor, word 3
-constexpr int kDropOffset = 0x7ffffff0;        // past every record: loads read 0, stores are dropped
-constexpr int64_t kMaxRecords = 0x7ff00000;
+// The planner keeps every offset a task really touches below 2^30 and
+// descriptors hold at most 2^30 bytes, so offsets in [2^30, 2^31) are out of
+// range: loads there read 0 and stores there are dropped.
+constexpr int64_t kMaxRecords = int64_t(1) << 30;
+constexpr int kDropOffset = 0x60000000;
+constexpr uint32_t kDropColumn = 0x40000000u;   // column offset of lanes past the image
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes)
 {
@@ -221,6 +231,7 @@ __device__ __forceinline__ void store_out<TrBF16>(__amdgpu_buffer_rsrc_t rs, int
 // Per-task constants.
 struct TaskGeom {
     int s0, y0, hs, a0, off, niter, ybase;
+    int emit0;                                 // first iteration that emits a row (a multiple of G)
 };
 
 // --------------------------------------------------------------------------
@@ -228,6 +239,12 @@ struct TaskGeom {
 // + G, G) rows of running column sums plus G mirror rows (slots 0..G-1 are
 // also written at L..L+G-1), so the taps of a whole group are read at
 // (per-group base) + (row * 256 bytes) without any per-row modulo.
+//
+// Iteration `it` reads input row ybase + it and emits output row
+// ybase + it - R.  The task starts 2R + 1 + pre rows above its first output
+// row, pre < G chosen so that emission starts on a group boundary: a group
+// either emits all of its rows or none, and the output offset of row j of a
+// group is one add away from the group's.
 // --------------------------------------------------------------------------
 template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE>
 __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
@@ -236,7 +253,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     constexpr bool kInt = Tr::kInt;
     constexpr int G = kWave / SEG;             // rows per group
     constexpr int PW = SEG * NPL;              // span capacity = LDS row width
-    constexpr int PF = 3;                      // groups of loads in flight
+    constexpr int PF = kPrefetch;
     constexpr int es = Tr::kSize;
     const int lane = threadIdx.x;
     const int jrow = lane / SEG;               // row pass: row within the group
@@ -261,7 +278,10 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     const char* dbase = reinterpret_cast<const char*>(ip.dst) + int64_t(tg.y0) * dstride;
     const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(dbase, int64_t(tg.hs - 1) * dstride + int64_t(WC) * es);
     const int s = tg.s0 + lane;                // this lane's column
-    const int out_voff = (s < WC) ? s * es : kDropOffset;
+    // Output row k of the task is stored at ocol + k * dstride: lanes past the
+    // image start out of range, rows past the task end beyond the descriptor.
+    const uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
+    const uint32_t dstr = uint32_t(dstride);
 
     // ---- row-pass chunk offsets ----
     // Each row segment loads a different input row, so the row offset is a
@@ -281,16 +301,17 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     }
     const int sstride32 = int(sstride);
     auto load = [&](Chunk<Tr, NPL>& ch, int g) {
-        int y = tg.ybase + g * G + jrow;       // clamped: rows past the task end are re-read, unused
-        y = y < 0 ? 0 : (y >= H ? H - 1 : y);
-        const int rowoff = (y - y_lo) * sstride32;
+        const int y = tg.ybase + g * G + jrow;
+        const int yc = y < 0 ? 0 : (y >= H ? H - 1 : y);
+        const bool zero_row = !replicate && yc != y;      // ZERO boundary: rows outside read as 0
+        const int rowoff = (yc - y_lo) * sstride32;       // rows past the task end: re-read, unused
         if constexpr (EDGE) {
             int vo[NPL];
 #pragma unroll
-            for (int i = 0; i < NPL; ++i) vo[i] = eoff[i] < 0 ? kDropOffset : eoff[i] + rowoff;
+            for (int i = 0; i < NPL; ++i) vo[i] = (eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
             load_chunk_elem<Tr, NPL>(ch, rs_src, vo, 0);
         } else {
-            load_chunk_vec<Tr, NPL>(ch, rs_src, vec_voff + rowoff, 0);
+            load_chunk_vec<Tr, NPL>(ch, rs_src, zero_row ? kDropOffset : vec_voff + rowoff, 0);
         }
     };
 
@@ -306,7 +327,6 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         wm[k] = ip.m[k];
     }
     const float dc = ip.dc32;
-    const int seg_lead = lane & ~(SEG - 1);    // first lane of this lane's row segment
 
     const int ngroups = (tg.niter + G - 1) / G;
     const int ngroups_pf = (ngroups + PF - 1) / PF * PF;
@@ -329,7 +349,8 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     __builtin_amdgcn_sched_barrier(0);
 
     Acc colacc = Acc(0);
-    float c2 = 0.0f;                           // column offset (float types)
+    float c2 = 0.0f;                           // T of the task's first row (float types)
+    float c2dc = 0.0f;
     int slot0 = 0;                             // ring slot of the group's first row
 
     auto group = [&](int g, Chunk<Tr, NPL>& bf) {
@@ -338,12 +359,13 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         // and the wait for a load comes PF groups after it was issued.
         __builtin_amdgcn_sched_barrier(0);
         Acc v[NPL];
-        float myoff = 0.0f;
+        float off = 0.0f;
         if constexpr (!kInt) {
-            // offset: the first span sample of this row (added back via the DC gain)
-            myoff = __shfl(Tr::unpack(bf.w, 0), seg_lead);
+            // offset of the group: the first span sample of its first row
+            // (lane 0), added back through the DC gain of the boxes below
+            off = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(bf.w, 0))));
 #pragma unroll
-            for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(bf.w, i) - myoff;
+            for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(bf.w, i) - off;
         } else {
 #pragma unroll
             for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(bf.w, i);
@@ -386,28 +408,31 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 #pragma unroll
                 for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
             } else {
-                const float cj = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(myoff), j * SEG));
-                t = cj * dc;
+                t = wf[0] * (Pj[tp[0]] - Pj[tm[0]]);
 #pragma unroll
-                for (int k = 0; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
-            }
-            if (!replicate) {
-                const int y = tg.ybase + it0 + j;
-                if (y < 0 || y >= H) t = Acc(0);
+                for (int k = 1; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
             }
             T[j] = t;
         }
-        if constexpr (!kInt) {
-            if (g == 0) c2 = T[0];
-        }
 
         // ---- running sums down the columns into the ring (Eq. alg1) ----
+        // Float types add each row as (T + off * dc) - c2: the group offset
+        // restores the row's true box sums, c2 keeps the column sums small.
+        float kg = 0.0f;
+        if constexpr (!kInt) {
+            const float odc = off * dc;
+            if (g == 0) {
+                c2 = T[0] + odc;
+                c2dc = c2 * dc;
+            }
+            kg = odc - c2;
+        }
         const int wbase = slot0 * kWave + lane;
         const int mbase = (slot0 == 0 ? L : slot0) * kWave + lane;
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             if constexpr (kInt) colacc += T[j];
-            else colacc += T[j] - c2;
+            else colacc += T[j] + kg;
             ring[wbase + j * kWave] = colacc;
             ring[mbase + j * kWave] = colacc;       // mirror copy (same slot unless slot0 == 0)
         }
@@ -424,23 +449,21 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
             bp[k] = a * kWave + lane;
             bm[k] = b * kWave + lane;
         }
+        const uint32_t og = (it0 >= tg.emit0) ? ocol + uint32_t(it0 - tg.emit0) * dstr : uint32_t(kDropOffset);
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            const int it = it0 + j;
-            const bool emit = (it >= 2 * R + 1) && (it < tg.niter);
-            const int soff = emit ? int(int64_t(it - 2 * R - 1) * dstride) : 0;   // row y0 + it - 2R - 1
-            const int voff = emit ? out_voff : kDropOffset;
+            const int voff = int(og + uint32_t(j) * dstr);
             if constexpr (kInt) {
                 uint64_t U = 0;
 #pragma unroll
                 for (int k = 0; k < KT; ++k)
                     U += uint64_t(wm[k]) * uint32_t(ring[bp[k] + j * kWave] - ring[bm[k] + j * kWave]);
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, voff, soff, 0);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, voff, 0, 0);
             } else {
-                float o = c2 * dc;
+                float o = c2dc;
 #pragma unroll
                 for (int k = 0; k < KT; ++k) o = fmaf(wf[k], ring[bp[k] + j * kWave] - ring[bm[k] + j * kWave], o);
-                store_out<Tr>(rs_dst, voff, soff, o);
+                store_out<Tr>(rs_dst, voff, 0, o);
             }
         }
         slot0 += G;
@@ -448,9 +471,8 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     };
 
     for (int g = 0; g < ngroups_pf; g += PF) {
-        group(g, buf[0]);
-        group(g + 1, buf[1]);
-        group(g + 2, buf[2]);
+#pragma unroll
+        for (int b = 0; b < PF; ++b) group(g + b, buf[b]);
     }
 }
 
@@ -458,16 +480,19 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 template <class Tr, int C, int SEG, int NPL, int KT>
 __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t* lds)
 {
+    constexpr int G = kWave / SEG;
     TaskGeom tg;
     const int strip = task % ip.nstrips;
     const int seg = task / ip.nstrips;
+    const int pre = (G - (2 * ip.R + 1) % G) % G;
     tg.s0 = strip * kWave;
     tg.y0 = seg * ip.hs;
     tg.hs = min(ip.hs, ip.H - tg.y0);
     tg.a0 = floor_div(tg.s0 - (ip.R + 1) * C, ip.align) * ip.align;
     tg.off = tg.s0 - tg.a0;
-    tg.niter = 2 * ip.R + 1 + tg.hs;
-    tg.ybase = tg.y0 - ip.R - 1;
+    tg.emit0 = 2 * ip.R + 1 + pre;
+    tg.niter = tg.emit0 + tg.hs;
+    tg.ybase = tg.y0 - ip.R - 1 - pre;
     const int WC = ip.W * C;
     const bool interior = ip.vec && tg.a0 >= 0 && tg.a0 + SEG * NPL <= WC;
     if (interior) stream_task<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);

@@ -20,6 +20,11 @@ extern const double kSigma0Value;
 
 constexpr int kWave = 64;          // CDNA wavefront width; also the strip width in samples
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies
+#ifndef RSG_PREFETCH
+#define RSG_PREFETCH 3
+#endif
+constexpr int kPrefetch = RSG_PREFETCH;   // groups of row loads in flight per wave
+constexpr int64_t kOffsetLimit = int64_t(1) << 30;   // every byte offset a task touches stays below this
 
 // Everything one image's kernel needs; plain data, copied to the device for
 // batched launches and passed by value for single-image launches.

@@ -93,8 +93,6 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     const int64_t ss = d.src_stride ? d.src_stride : WC;
     const int64_t ds = d.dst_stride ? d.dst_stride : WC;
     if (ss < WC || ds < WC) return set_error(RSG_EINVAL, "row stride smaller than W*C");
-    if ((ss > ds ? ss : ds) * 8 > (int64_t(1) << 30) / 1024)
-        return set_error(RSG_EUNSUPPORTED, "row stride too large (%lld elements)", (long long)(ss > ds ? ss : ds));
     const int es = dtype_size(d.dt);
     {   // source and destination must not overlap
         const char* s0 = static_cast<const char*>(d.src);
@@ -183,6 +181,18 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     int hs = 0;
     if (!tuned_hs(d.dt, C, R, &hs)) hs = default_hs(d.H, p.nstrips, R, p.lds_bytes);
     hs = std::max(1, std::min(hs, d.H));
+    {   // every offset a task touches (rows ybase .. ybase + its padded
+        // iteration count, times the larger stride) must stay below 2^30
+        const int64_t stride_b = std::max(ss, ds) * es;
+        auto fits = [&](int h) {
+            const int64_t rows = int64_t(h) + 2 * R + 1 + (p.G - 1) + int64_t(kPrefetch + 1) * p.G;
+            return rows * stride_b + WC * es <= kOffsetLimit;
+        };
+        while (hs > 1 && !fits(hs)) hs = (hs + 1) / 2;
+        if (!fits(hs))
+            return set_error(RSG_EUNSUPPORTED, "row stride too large for a tile (%lld bytes, box half-width %d)",
+                             (long long)stride_b, R);
+    }
     p.hs = hs;
     p.nsegs = (d.H + hs - 1) / hs;
     const int64_t nt = int64_t(p.nstrips) * p.nsegs;

@@ -1,0 +1,243 @@
+"""Batched and served filtering on the device, through the C ABI.
+
+Every image of a persistent batch launch, and every served request, must be
+bit-identical to filtering that image alone (tile shapes depend on the image
+only), and the single-image results are themselves checked against the
+oracle here on sampled points (uint8 exactly, FP32 within 1e-5 of max|ref|)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synthimg
+from gpu_util import decode, from_device, to_device
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+def _rsg():
+    import paper_1107_4958_amd as rsg
+    return rsg
+
+
+def _alone(src, sigma, K, boundary=0):
+    import torch
+    out = _rsg().filter_tensor(src, sigma, K, boundary)
+    torch.cuda.synchronize()
+    return out
+
+
+def _spot_check(img, out, dtype, sigma, K, boundary=0, n=200, seed=0):
+    """Sampled parity of one device result with the oracle."""
+    b = oracle.boxes(sigma, K)
+    im3 = img[..., None] if img.ndim == 2 else img
+    o3 = out[..., None] if out.ndim == 2 else out
+    rng = np.random.default_rng(seed)
+    H, W, C = im3.shape
+    ys, xs, cs = rng.integers(0, H, n), rng.integers(0, W, n), rng.integers(0, C, n)
+    if dtype == "u8":
+        ref = oracle.box_filter_u8_points(im3, b["r"], b["m"], b["G"], ys, xs, cs, boundary=boundary)
+        assert np.array_equal(o3[ys, xs, cs], ref)
+    else:
+        ref = oracle.box_filter_points(decode(im3, dtype), b["r"], b["w32"].astype(np.float64), ys, xs, cs,
+                                       boundary=boundary)
+        den = max(float(np.max(np.abs(im3))), 1e-30)
+        assert float(np.max(np.abs(o3[ys, xs, cs].astype(np.float64) - ref))) / den <= FP32_TOL
+
+
+def _mixed_images():
+    """Ragged sizes, every dtype and channel count, sigma 0.7..40, K 1..5."""
+    specs = [
+        (1, 1, 1, "u8", 2.0, 3), (37, 523, 3, "u8", 7.5, 4), (300, 17, 1, "f32", 5.0, 3),
+        (129, 1000, 1, "f32", 12.0, 5), (61, 211, 3, "f16", 6.0, 5), (70, 90, 4, "bf16", 2.5, 3),
+        (257, 259, 2, "u8", 32.0, 5), (513, 127, 1, "u8", 0.7, 2), (96, 96, 4, "f32", 40.0, 4),
+        (1024, 768, 3, "u8", 3.0, 4), (640, 480, 1, "f16", 18.0, 3), (5, 3000, 1, "f32", 1.0, 1),
+    ]
+    out = []
+    for i, (H, W, C, dt, sg, K) in enumerate(specs):
+        out.append(dict(H=H, W=W, C=C, dtype=dt, sigma=sg, K=K, img=synthimg.crop_pool(H, W, C, dt, 50 + i)))
+    return out
+
+
+def test_batch_mixed_identical_to_alone():
+    import torch
+    rsg = _rsg()
+    items = _mixed_images()
+    srcs = [to_device(it["img"], it["dtype"]) for it in items]
+    dsts = [torch.full_like(s, 0) for s in srcs]
+    rsg.filter_batch_tensors(srcs, dsts, [it["sigma"] for it in items], [it["K"] for it in items])
+    torch.cuda.synchronize()
+    for it, s, d in zip(items, srcs, dsts):
+        alone = from_device(_alone(s, it["sigma"], it["K"]), it["dtype"])
+        got = from_device(d, it["dtype"])
+        assert np.array_equal(got.view(np.uint8), alone.view(np.uint8)), (it["H"], it["W"], it["C"], it["dtype"])
+        if it["dtype"] in ("u8", "f32"):
+            _spot_check(it["img"], got, it["dtype"], it["sigma"], it["K"])
+
+
+def test_batch_zero_boundary_and_repeat():
+    """ZERO boundary in a batch; a second launch reusing the workspace gives
+    the same bits."""
+    import torch
+    rsg = _rsg()
+    items = _mixed_images()[:6]
+    srcs = [to_device(it["img"], it["dtype"]) for it in items]
+    d1 = [torch.empty_like(s) for s in srcs]
+    d2 = [torch.empty_like(s) for s in srcs]
+    sg = [it["sigma"] for it in items]
+    Ks = [it["K"] for it in items]
+    ws = rsg.filter_batch_tensors(srcs, d1, sg, Ks, boundary=rsg.RSG_ZERO)
+    rsg.filter_batch_tensors(srcs, d2, sg, Ks, boundary=rsg.RSG_ZERO, workspace=ws)
+    torch.cuda.synchronize()
+    for it, s, a, b in zip(items, srcs, d1, d2):
+        alone = from_device(_alone(s, it["sigma"], it["K"], rsg.RSG_ZERO), it["dtype"])
+        assert np.array_equal(from_device(a, it["dtype"]).view(np.uint8), alone.view(np.uint8))
+        assert np.array_equal(from_device(b, it["dtype"]).view(np.uint8), alone.view(np.uint8))
+        if it["dtype"] == "u8":
+            _spot_check(it["img"], from_device(a, "u8"), "u8", it["sigma"], it["K"], rsg.RSG_ZERO)
+
+
+def test_batch_256_three_channel_u8():
+    """The mixed workload: 256 3-channel uint8 images of side 64..2048,
+    sigma log-uniform in [1, 30], K = 4, one launch."""
+    import torch
+    rsg = _rsg()
+    specs = synthimg.batch_specs(256)
+    imgs = [synthimg.crop_pool(s["H"], s["W"], s["C"], "u8", s["seed"]) for s in specs]
+    srcs = [to_device(im, "u8") for im in imgs]
+    dsts = [torch.empty_like(s) for s in srcs]
+    rsg.filter_batch_tensors(srcs, dsts, [s["sigma"] for s in specs], [s["K"] for s in specs])
+    torch.cuda.synchronize()
+    for i in range(0, 256, 5):
+        alone = from_device(_alone(srcs[i], specs[i]["sigma"], specs[i]["K"]), "u8")
+        got = from_device(dsts[i], "u8")
+        assert np.array_equal(got, alone), i
+        if i % 25 == 0:
+            _spot_check(imgs[i], got, "u8", specs[i]["sigma"], specs[i]["K"], seed=i)
+
+
+def test_batch_errors():
+    import torch
+    rsg = _rsg()
+    a = torch.zeros(64, 64, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    d = rsg.make_desc(a, b, 3.0, 3)
+    need = rsg.rsg_filter_batch_workspace([d])
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rsg.RsgError) as e:
+        rsg.rsg_filter_batch([d], ws.data_ptr(), need - 1, torch.cuda.current_stream().cuda_stream)
+    assert e.value.code == rsg.RSG_ENOMEM
+    bad = rsg.make_desc(a, b, 3.0, 9)
+    with pytest.raises(rsg.RsgError):
+        rsg.rsg_filter_batch_workspace([bad])
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+def _server(arena, **kw):
+    rsg = _rsg()
+    cfg = rsg.rsg_server_config()
+    cfg.d_arena = arena.data_ptr()
+    cfg.arena_bytes = arena.numel()
+    cfg.hbm_budget = kw.get("hbm_budget", 0)
+    cfg.max_inflight = kw.get("max_inflight", 4)
+    cfg.n_streams = kw.get("n_streams", 2)
+    cfg.queue_depth = kw.get("queue_depth", 64)
+    cfg.max_batch = kw.get("max_batch", 8)
+    return rsg.rsg_server_create(cfg)
+
+
+def _wait_all(srv, tickets, timeout_s=60.0):
+    rsg = _rsg()
+    stats = {}
+    t_end = time.monotonic() + timeout_s
+    while len(stats) < len(tickets):
+        assert time.monotonic() < t_end, "served requests did not finish in %.0f s" % timeout_s
+        for t in tickets:
+            if t not in stats:
+                st = rsg.rsg_poll(srv, t)
+                if st.done:
+                    stats[t] = (st.status, st.t_submit_ns, st.t_admit_ns, st.t_start_ns, st.t_done_ns)
+        time.sleep(0.0005)
+    return stats
+
+
+def test_serve_mixed_requests_identical_to_alone():
+    import torch
+    rsg = _rsg()
+    items = _mixed_images()
+    srcs = [to_device(it["img"], it["dtype"]) for it in items]
+    dsts = [torch.empty_like(s) for s in srcs]
+    arena = torch.empty(32 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    srv = _server(arena)
+    try:
+        tickets = [rsg.rsg_submit(srv, rsg.make_desc(s, d, it["sigma"], it["K"])) for s, d, it in zip(srcs, dsts, items)]
+        stats = _wait_all(srv, tickets)
+        for t in tickets:
+            status, ts, ta, tb, td = stats[t]
+            assert status == rsg.RSG_OK
+            assert ts <= ta <= tb <= td
+        with pytest.raises(rsg.RsgError) as e:   # a reported ticket is forgotten
+            rsg.rsg_poll(srv, tickets[0])
+        assert e.value.code == rsg.RSG_ENOTFOUND
+    finally:
+        rsg.rsg_server_destroy(srv)
+    for it, s, d in zip(items, srcs, dsts):
+        alone = from_device(_alone(s, it["sigma"], it["K"]), it["dtype"])
+        assert np.array_equal(from_device(d, it["dtype"]).view(np.uint8), alone.view(np.uint8))
+
+
+def test_serve_budget_and_queue_limits():
+    """ENOMEM for a request larger than the HBM budget, EBUSY once the
+    admission queue is full, and every accepted request still completes."""
+    import torch
+    rsg = _rsg()
+    big = torch.rand(8192, 8192, device="cuda") * 255       # 256 MiB in, 256 MiB out: ~1 ms at sigma 32
+    outs = [torch.empty_like(big) for _ in range(12)]
+    arena = torch.empty(8 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    one = 2 * big.numel() * 4
+    srv = _server(arena, hbm_budget=one, queue_depth=2, max_inflight=1, n_streams=1, max_batch=1)
+    try:
+        huge = torch.empty(8192, 8193, device="cuda")
+        with pytest.raises(rsg.RsgError) as e:
+            rsg.rsg_submit(srv, rsg.make_desc(huge, torch.empty_like(huge), 32.0, 3))
+        assert e.value.code == rsg.RSG_ENOMEM
+        accepted, busy = [], 0
+        for o in outs:                                        # a burst: one admitted at a time
+            try:
+                accepted.append((rsg.rsg_submit(srv, rsg.make_desc(big, o, 32.0, 3)), o))
+            except rsg.RsgError as err:
+                assert err.code == rsg.RSG_EBUSY
+                busy += 1
+        assert busy >= 1 and len(accepted) >= 2
+        stats = _wait_all(srv, [t for t, _ in accepted])
+        assert all(v[0] == rsg.RSG_OK for v in stats.values())
+    finally:
+        rsg.rsg_server_destroy(srv)
+    ref = _alone(big, 32.0, 3)
+    for _, o in accepted:
+        assert torch.equal(o, ref)
+
+
+def test_serve_destroy_drains():
+    """Destroying the server with requests queued finishes them first."""
+    import torch
+    rsg = _rsg()
+    src = to_device(synthimg.crop_pool(1024, 1024, 3, "u8", 9), "u8")
+    outs = [torch.zeros_like(src) for _ in range(6)]
+    arena = torch.empty(8 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    srv = _server(arena, max_inflight=2, max_batch=2)
+    for o in outs:
+        rsg.rsg_submit(srv, rsg.make_desc(src, o, 5.0, 4))
+    rsg.rsg_server_destroy(srv)
+    torch.cuda.synchronize()
+    ref = _alone(src, 5.0, 4)
+    for o in outs:
+        assert torch.equal(o, ref)
