@@ -238,7 +238,7 @@ struct TaskGeom {
 // The streaming loop of one task.  The column ring keeps L = roundup(2R + 1
 // + G, G) rows of running column sums plus G mirror rows (slots 0..G-1 are
 // also written at L..L+G-1), so the taps of a whole group are read at
-// (per-group base) + (row * 256 bytes) without any per-row modulo.
+// (per-group base) + (row * ring pitch) without any per-row modulo.
 //
 // Iteration `it` reads input row ybase + it and emits output row
 // ybase + it - R.  The task starts 2R + 1 + pre rows above its first output
@@ -252,8 +252,11 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     using Acc = typename Tr::Acc;
     constexpr bool kInt = Tr::kInt;
     constexpr int G = kWave / SEG;             // rows per group
-    constexpr int PW = SEG * NPL;              // span capacity = LDS row width
+    constexpr int PW = SEG * NPL;              // span capacity
+    constexpr int PP = row_tile_pitch(SEG, NPL);   // LDS pitch of the row-sum tile
+    constexpr int RP = kWave;                      // LDS pitch of the column ring
     constexpr int PF = kPrefetch;
+    static_assert(PF % 2 == 0, "the loop alternates the two row tiles, so it unrolls by an even count");
     constexpr int es = Tr::kSize;
     const int lane = threadIdx.x;
     const int jrow = lane / SEG;               // row pass: row within the group
@@ -265,8 +268,8 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     const int WC = W * C;
     const bool replicate = (ip.boundary == RSG_REPLICATE);
 
-    Acc* P = reinterpret_cast<Acc*>(lds);      // G rows x PW running sums
-    Acc* ring = P + G * PW;                    // (L + G) rows x 64 column sums
+    Acc* P = reinterpret_cast<Acc*>(lds);      // 2 tiles of G rows x PW running sums (pitch PP)
+    Acc* ring = P + 2 * G * PP;                // (L + G) rows x 64 column sums (pitch RP)
 
     // ---- source / destination descriptors (task-relative row offsets) ----
     const int y_lo = max(0, tg.ybase);        // loads clamp rows into [y_lo, H - 1]
@@ -329,7 +332,6 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     const float dc = ip.dc32;
 
     const int ngroups = (tg.niter + G - 1) / G;
-    const int ngroups_pf = (ngroups + PF - 1) / PF * PF;
 
     // Prologue: the first PF groups' loads, in order, each followed by G
     // dropped stores, so the memory-operation sequence before the loop
@@ -349,20 +351,23 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     __builtin_amdgcn_sched_barrier(0);
 
     Acc colacc = Acc(0);
-    float c2 = 0.0f;                           // T of the task's first row (float types)
+    float c2 = 0.0f;                           // column offset (float types): T of the task's first row
     float c2dc = 0.0f;
-    int slot0 = 0;                             // ring slot of the group's first row
+    int slot0 = 0;                             // ring slot of the first row of the queued group
+    Acc Tq[G];                                 // row-pass result of the group queued for the column pass
+    float kq = 0.0f;                           // its offset correction (float types)
 
-    auto group = [&](int g, Chunk<Tr, NPL>& bf) {
-        // Consume this group's chunk, then reuse its registers for the load
-        // of group g + PF, so the loop-carried buffers are written in place
-        // and the wait for a load comes PF groups after it was issued.
+    // Row pass, first half: consume the group's chunk, reuse its registers
+    // for the load of group g + PF (so the loop-carried buffers are written
+    // in place and each load is waited for PF groups after it was issued),
+    // scan the rows and write them to the LDS tile.  Returns the group's
+    // offset (float types): the first span sample of its first row (lane 0),
+    // subtracted from every sample and restored through the DC gain.
+    auto row_scan = [&](int g, Chunk<Tr, NPL>& bf, int t) -> float {
         __builtin_amdgcn_sched_barrier(0);
         Acc v[NPL];
         float off = 0.0f;
         if constexpr (!kInt) {
-            // offset of the group: the first span sample of its first row
-            // (lane 0), added back through the DC gain of the boxes below
             off = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(bf.w, 0))));
 #pragma unroll
             for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(bf.w, i) - off;
@@ -373,9 +378,8 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         __builtin_amdgcn_sched_barrier(0);
         load(bf, g + PF);
         __builtin_amdgcn_sched_barrier(0);
-        const int it0 = g * G;
 
-        // ---- running sum of this lane's row over its span (Eq. alg1) ----
+        // running sum of this lane's row over its span (Eq. alg1)
 #pragma unroll
         for (int i = C; i < NPL; ++i) v[i] = v[i] + v[i - C];
 #pragma unroll
@@ -385,70 +389,87 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 #pragma unroll
             for (int i = c; i < NPL; i += C) v[i] = v[i] + ex;
         }
-        {   // 16-byte stores (NPL is a multiple of 4)
-            using Acc4 = typename std::conditional<kInt, uint4, float4>::type;
-            Acc4* dst4 = reinterpret_cast<Acc4*>(P + jrow * PW + q * NPL);
+        using Acc4 = typename std::conditional<kInt, uint4, float4>::type;
+        Acc4* dst4 = reinterpret_cast<Acc4*>(P + (t * G + jrow) * PP + q * NPL);   // 16-byte stores
 #pragma unroll
-            for (int h = 0; h < NPL / 4; ++h) {
-                Acc4 t4;
-                t4.x = v[4 * h + 0]; t4.y = v[4 * h + 1]; t4.z = v[4 * h + 2]; t4.w = v[4 * h + 3];
-                dst4[h] = t4;
-            }
+        for (int h = 0; h < NPL / 4; ++h) {
+            Acc4 t4;
+            t4.x = v[4 * h + 0]; t4.y = v[4 * h + 1]; t4.z = v[4 * h + 2]; t4.w = v[4 * h + 3];
+            dst4[h] = t4;
         }
-        wave_lds_fence();
+        return off;
+    };
 
-        // ---- box differences along the rows (Eq. indep); lane = column ----
-        Acc T[G];
+    // Row pass, second half (after the tile is visible): box differences
+    // along the rows (Eq. indep), lane = column.  The reads are issued as one
+    // batch (row_reads) before any of them is used (row_combine).
+    using Taps = Acc[G][2 * KT];
+    auto row_reads = [&](Taps& pv, int t) {
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            const Acc* Pj = P + j * PW;
+            const Acc* Pj = P + (t * G + j) * PP;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                pv[j][2 * k] = Pj[tp[k]];
+                pv[j][2 * k + 1] = Pj[tm[k]];
+            }
+        }
+    };
+    auto row_combine = [&](const Taps& pv, Acc (&T)[G]) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
             Acc t;
             if constexpr (kInt) {
                 t = 0;
 #pragma unroll
-                for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
+                for (int k = 0; k < KT; ++k) t += __umul24(wm[k], pv[j][2 * k] - pv[j][2 * k + 1]);
             } else {
-                t = wf[0] * (Pj[tp[0]] - Pj[tm[0]]);
+                t = wf[0] * (pv[j][0] - pv[j][1]);
 #pragma unroll
-                for (int k = 1; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
+                for (int k = 1; k < KT; ++k) t = fmaf(wf[k], pv[j][2 * k] - pv[j][2 * k + 1], t);
             }
             T[j] = t;
         }
+    };
 
-        // ---- running sums down the columns into the ring (Eq. alg1) ----
-        // Float types add each row as (T + off * dc) - c2: the group offset
-        // restores the row's true box sums, c2 keeps the column sums small.
-        float kg = 0.0f;
-        if constexpr (!kInt) {
-            const float odc = off * dc;
-            if (g == 0) {
-                c2 = T[0] + odc;
-                c2dc = c2 * dc;
-            }
-            kg = odc - c2;
-        }
-        const int wbase = slot0 * kWave + lane;
-        const int mbase = (slot0 == 0 ? L : slot0) * kWave + lane;
+    // Column pass, first half: running sums down the columns (Eq. alg1) of
+    // the queued group into the ring.  Float types add each row as
+    // (T + off * dc) - c2: the offset restores the row's true box sums, c2
+    // keeps the column sums small.
+    auto col_push = [&]() {
+        const int wbase = slot0 * RP + lane;
+        const int mbase = (slot0 == 0 ? L : slot0) * RP + lane;
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            if constexpr (kInt) colacc += T[j];
-            else colacc += T[j] + kg;
-            ring[wbase + j * kWave] = colacc;
-            ring[mbase + j * kWave] = colacc;       // mirror copy (same slot unless slot0 == 0)
+            if constexpr (kInt) colacc += Tq[j];
+            else colacc += Tq[j] + kq;
+            ring[wbase + j * RP] = colacc;
+            ring[mbase + j * RP] = colacc;          // mirror copy (same slot unless slot0 == 0)
         }
-        wave_lds_fence();
+    };
 
-        // ---- box differences down the columns for rows it - R (Eq. indep) ----
-        int bp[KT], bm[KT];
+    // Column pass, second half (after the ring rows are visible): box
+    // differences down the columns (Eq. indep) for the rows R behind the
+    // queued group's rows (col_reads issues the reads, col_combine uses them
+    // and stores the outputs).
+    auto col_reads = [&](Taps& rv) {
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
             int a = slot0 - R + ip.r[k];
             int b = slot0 - R - ip.r[k] - 1;
             a += (a < 0) ? L : 0;
             b += (b < 0) ? L : 0;
-            bp[k] = a * kWave + lane;
-            bm[k] = b * kWave + lane;
+            const int bp = a * RP + lane;
+            const int bm = b * RP + lane;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                rv[j][2 * k] = ring[bp + j * RP];
+                rv[j][2 * k + 1] = ring[bm + j * RP];
+            }
         }
+    };
+    auto col_combine = [&](int gq, const Taps& rv) {
+        const int it0 = gq * G;
         const uint32_t og = (it0 >= tg.emit0) ? ocol + uint32_t(it0 - tg.emit0) * dstr : uint32_t(kDropOffset);
 #pragma unroll
         for (int j = 0; j < G; ++j) {
@@ -456,23 +477,79 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
             if constexpr (kInt) {
                 uint64_t U = 0;
 #pragma unroll
-                for (int k = 0; k < KT; ++k)
-                    U += uint64_t(wm[k]) * uint32_t(ring[bp[k] + j * kWave] - ring[bm[k] + j * kWave]);
+                for (int k = 0; k < KT; ++k) U += uint64_t(wm[k]) * uint32_t(rv[j][2 * k] - rv[j][2 * k + 1]);
                 __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, voff, 0, 0);
             } else {
                 float o = c2dc;
 #pragma unroll
-                for (int k = 0; k < KT; ++k) o = fmaf(wf[k], ring[bp[k] + j * kWave] - ring[bm[k] + j * kWave], o);
+                for (int k = 0; k < KT; ++k) o = fmaf(wf[k], rv[j][2 * k] - rv[j][2 * k + 1], o);
                 store_out<Tr>(rs_dst, voff, 0, o);
             }
         }
-        slot0 += G;
-        slot0 -= (slot0 >= L) ? L : 0;
     };
 
-    for (int g = 0; g < ngroups_pf; g += PF) {
+    auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
 #pragma unroll
-        for (int b = 0; b < PF; ++b) group(g + b, buf[b]);
+        for (int j = 0; j < G; ++j) {
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, 0);
+            else store_out<Tr>(rs_dst, kDropOffset - 64 * (base + j), 0, 0.0f);
+        }
+    };
+
+    // Software pipeline.  Step g (g >= 1):
+    //   1. row pass of group g + 1 up to its tile write (tile (g + 1) & 1),
+    //   2. row differences of group g from the tile reads issued in step g - 1,
+    //   3. column outputs of group g - 1 from the ring reads issued in step g - 1,
+    //   4. column sums of group g into the ring,
+    //   5. one fence, then the reads for steps 2 and 3 of step g + 1.
+    // The reads of step 5 are served while step g + 1 runs its row scan.
+    // Steps with no real rows (before the first emitted row, past the task)
+    // store to dropped offsets, so every step issues the same memory
+    // operations and the loop's waits stay exact.
+    Taps pv, rv;
+    float off_cur = row_scan(0, buf[0], 0);      // group 0
+    dropped_stores(PF * G);
+    wave_lds_fence();
+    row_reads(pv, 0);
+    {   // step 0: group 1's row scan, group 0's row differences and column sums
+        const float off_next = row_scan(1, buf[1 % PF], 1);
+        Acc T[G];
+        row_combine(pv, T);
+        if constexpr (!kInt) {
+            const float odc = off_cur * dc;
+            c2 = T[0] + odc;
+            c2dc = c2 * dc;
+            kq = odc - c2;
+        }
+        dropped_stores(PF * G + G);
+#pragma unroll
+        for (int j = 0; j < G; ++j) Tq[j] = T[j];
+        col_push();
+        wave_lds_fence();
+        row_reads(pv, 1);
+        col_reads(rv);
+        off_cur = off_next;
+    }
+    const int nsteps = (ngroups + PF - 1) / PF * PF;   // steps 1 .. nsteps: column outputs of groups 0 .. nsteps - 1
+    for (int g = 1; g < nsteps + 1; g += PF) {
+#pragma unroll
+        for (int b = 0; b < PF; ++b) {
+            const int gg = g + b;
+            const float off_next = row_scan(gg + 1, buf[(2 + b) % PF], b & 1);
+            Acc T[G];
+            row_combine(pv, T);
+            col_combine(gg - 1, rv);
+            slot0 += G;
+            slot0 -= (slot0 >= L) ? L : 0;
+#pragma unroll
+            for (int j = 0; j < G; ++j) Tq[j] = T[j];
+            if constexpr (!kInt) kq = off_cur * dc - c2;
+            col_push();
+            wave_lds_fence();
+            row_reads(pv, b & 1);                // tile of group gg + 1
+            col_reads(rv);
+            off_cur = off_next;
+        }
     }
 }
 
@@ -512,7 +589,7 @@ __device__ __forceinline__ int xcd_task(int b, int n)
 }
 
 template <class Tr, int C, int SEG, int NPL, int KT>
-__global__ __launch_bounds__(64) void k_single(ImgParams ip)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_single(ImgParams ip)
 {
     extern __shared__ uint32_t lds[];
     run_task<Tr, C, SEG, NPL, KT>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
@@ -522,7 +599,7 @@ __global__ __launch_bounds__(64) void k_single(ImgParams ip)
 // (image, task) items off a shared counter until the list is exhausted.
 // The image's scan layout (SEG, NPL) selects among four instantiations.
 template <class Tr, int C, int KT, int S0, int N0, int S1, int N1, int S2, int N2, int S3, int N3>
-__global__ __launch_bounds__(64) void k_batch(const ImgParams* __restrict__ imgs,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_batch(const ImgParams* __restrict__ imgs,
                                               const BatchTask* __restrict__ tasks, int ntasks,
                                               unsigned* __restrict__ counter)
 {

@@ -21,7 +21,7 @@ extern const double kSigma0Value;
 constexpr int kWave = 64;          // CDNA wavefront width; also the strip width in samples
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies
 #ifndef RSG_PREFETCH
-#define RSG_PREFETCH 3
+#define RSG_PREFETCH 2
 #endif
 constexpr int kPrefetch = RSG_PREFETCH;   // groups of row loads in flight per wave
 constexpr int64_t kOffsetLimit = int64_t(1) << 30;   // every byte offset a task touches stays below this
@@ -99,6 +99,18 @@ inline void scan_layout(int C, int i, int* seg, int* npl)
     *seg = segs[i];
     *npl = (C == 3) ? n3[i] : n1[i];
 }
+// LDS row pitch (in 32-bit words) of the row-sum tiles.  The compiler pairs
+// reads of one lane from consecutive tile rows into one ds_read2; a pitch of
+// 32 (mod 64) words puts the pair in opposite halves of the 64 banks.  The
+// column ring keeps the dense 64-word pitch (one word per lane).
+constexpr int row_tile_pitch(int seg, int npl) { return seg * npl + 32; }
+// Two row tiles (double-buffered) and the ring of L + G rows.
+inline uint32_t tile_lds_bytes(int seg, int npl, int L)
+{
+    const int G = kWave / seg;
+    return uint32_t(4 * (2 * G * row_tile_pitch(seg, npl) + (L + G) * kWave));
+}
+
 // h_stage: optional pinned host buffer of >= batch_workspace_bytes() used to
 // stage the work list (must not be reused before the copy has executed);
 // NULL stages through pageable memory.

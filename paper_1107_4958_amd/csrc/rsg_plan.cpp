@@ -172,7 +172,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     }
     p.G = kWave / seg;
     p.L = (2 * R + 1 + p.G + p.G - 1) / p.G * p.G;
-    p.lds_bytes = uint32_t(4 * (p.G * seg * npl + (p.L + p.G) * kWave));
+    p.lds_bytes = tile_lds_bytes(seg, npl, p.L);
     if (p.lds_bytes > kLdsLimit)
         return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", p.lds_bytes, kLdsLimit);
     p.nstrips = int((WC + kWave - 1) / kWave);
