@@ -2,18 +2,21 @@
 
 A step is one filter of one image through the C ABI (rsg_gauss_filter: the
 host fit is cached, the fused row + column kernel runs on the device).  The
-default workload is the headline configuration: one 4096 x 4096
-single-channel FP32 synthetic 1/f image, sigma = 8, K = 3 boxes, replicate
-boundary.  Inputs rotate over enough buffer pairs (> 512 MB) that no step
-finds its image in the 256 MB last-level cache, and are resident in HBM
-before the timed region starts.
+headline workload is one 4096 x 4096 single-channel FP32 synthetic 1/f image,
+sigma = 8, K = 3 boxes, replicate boundary.  Inputs rotate over enough buffer
+pairs (> 512 MB) that no step finds its image in the 256 MB last-level cache,
+and are resident in HBM before the timed region starts.
 
-Prints ONE JSON line (rank 0): metric/value/unit, the roofline of the fused
-kernel (algorithmic bytes per launch / average launch time from HIP events
-on the launch stream, against 8 TB/s HBM3E), the CPU oracle baseline, and a
-uint8 variant of the same configuration.  --full adds the sigma x K grid,
-the mixed batch (one persistent launch), the 8192^2 precision forms and the
-served latency percentiles.
+Prints ONE JSON line: metric/value/unit of the headline, the roofline of the
+fused kernel (algorithmic bytes per launch / average launch time from HIP
+events on the launch stream, against 8 TB/s HBM3E; HBM traffic from the
+committed rocprofv3 counter summary when it was taken on the current kernel
+sources), the CPU oracle baseline, the uint8 form of the headline and, unless
+--quick: the sigma x K grid at 4096^2 (uint8 and FP32), the mixed batch (256
+three-channel uint8 images in one persistent launch against the same images
+filtered one launch each), the 8192^2 precision forms with their normalised
+RMS error against the FP64 oracle, and the served request stream's p50/p99
+latency and throughput.
 """
 from __future__ import annotations
 
@@ -37,20 +40,25 @@ ES = {"u8": 1, "f32": 4, "f16": 2, "bf16": 2}
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("rsg_device.h", "rsg_dispatch.h", "rsg_plan.cpp"):
+    for name in ("rsg_device.h", "rsg_dispatch.h", "rsg_plan.cpp", "rsg_internal.h"):
         with open(os.path.join(ROOT, "paper_1107_4958_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    tune = os.path.join(ROOT, "paper_1107_4958_amd", "tune_gfx950.txt")
+    if os.path.exists(tune):
+        with open(tune, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def traffic_record(workload_key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+    it was taken on the current kernel sources and tuning table; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(workload_key)
+        with open(path) as f:
+            rec = json.load(f).get(workload_key)
     except (OSError, ValueError):
         return None
     if not rec or rec.get("kernel_sha") != kernel_source_hash():
@@ -58,43 +66,46 @@ def traffic_record(workload_key: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def torch_dtype(name):
-    import torch
-    return {"u8": torch.uint8, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[name]
-
-
-def make_image(H, W, C, dtype, seed):
-    import synthimg
-    img = synthimg.image(H, W, C, dtype, seed)
-    return img
-
-
 def to_dev(img, dtype):
     import torch
     if dtype == "bf16":
-        return torch.from_numpy(img.view(np.int16)).view(torch.bfloat16).cuda()
-    return torch.from_numpy(img).cuda()
+        return torch.from_numpy(np.ascontiguousarray(img).view(np.int16)).view(torch.bfloat16).cuda()
+    return torch.from_numpy(np.ascontiguousarray(img)).cuda()
 
 
-def time_single(dtype, H, W, C, sigma, K, steps, warmup, seed=2, min_pool_bytes=640 << 20):
-    """Average launch time (ms) of rsg_gauss_filter over `steps` launches on
-    rotating buffers, timed with HIP events on the launch stream."""
+def from_dev(t, dtype):
+    import torch
+    if dtype == "bf16":
+        return t.view(torch.int16).cpu().numpy().view(np.uint16)
+    return t.cpu().numpy()
+
+
+def decode(a, dtype):
+    import synthimg
+    if dtype == "bf16":
+        return synthimg.bf16_bits_to_f32(a).astype(np.float64)
+    return a.astype(np.float64)
+
+
+def time_image(img, dtype, sigma, K, steps, warmup, min_pool_bytes=640 << 20):
+    """Average launch time (ms) of rsg_gauss_filter on `img` over `steps`
+    launches on rotating buffers, timed with HIP events on the launch stream.
+    Returns (ms, last output tensor)."""
     import torch
     import paper_1107_4958_amd as rsg
-    img = make_image(H, W, C, dtype, seed)
     base = to_dev(img, dtype)
+    H, W = img.shape[:2]
+    C = img.shape[2] if img.ndim == 3 else 1
     pair = 2 * base.numel() * base.element_size()
-    npairs = max(4, int(math.ceil(min_pool_bytes / pair)))
+    npairs = max(2, int(math.ceil(min_pool_bytes / pair)))
     srcs = [base] + [base.clone() for _ in range(npairs - 1)]
     dsts = [torch.empty_like(base) for _ in range(npairs)]
     stream = torch.cuda.current_stream()
-    h = stream.cuda_stream
-    shape = (H, W, C)
-    dt = rsg.DTYPE_NAMES[dtype]
+    code = rsg.tensor_dtype_code(base)
 
     def launch(i):
-        rsg.rsg_gauss_filter(srcs[i % npairs].data_ptr(), dsts[i % npairs].data_ptr(), H, W, C, dt, sigma, K,
-                             rsg.RSG_REPLICATE, h)
+        rsg.rsg_gauss_filter(srcs[i % npairs].data_ptr(), dsts[i % npairs].data_ptr(), H, W, C, code, sigma, K,
+                             rsg.RSG_REPLICATE, stream.cuda_stream)
 
     for i in range(warmup):
         launch(i)
@@ -106,8 +117,7 @@ def time_single(dtype, H, W, C, sigma, K, steps, warmup, seed=2, min_pool_bytes=
         launch(i)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    return ms, img, dsts[(steps - 1) % npairs], shape
+    return e0.elapsed_time(e1) / steps, dsts[(steps - 1) % npairs]
 
 
 def roofline(dtype, H, W, C, ms, traffic=None):
@@ -118,38 +128,197 @@ def roofline(dtype, H, W, C, ms, traffic=None):
             "algorithmic_bytes_per_launch": int(alg)}
 
 
-def cpu_baseline(dtype, H, W, sigma, K, seed=2):
-    """The oracle (FP64 direct box sums, OpenMP) timed on one full image."""
+def cpu_baseline(img, dtype, sigma, K, rows):
+    """The oracle (FP64 direct box sums, OpenMP) timed on the first `rows`
+    rows of the workload image (a bounded sample), scaled to Gpixel/s."""
     import oracle
     b = oracle.boxes(sigma, K)
-    img = make_image(H, W, 1, dtype, seed)
+    sample = np.ascontiguousarray(img[:rows])
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     if dtype == "u8":
-        oracle.box_filter_u8(img, b["r"], b["m"], b["G"])
+        oracle.box_filter_u8(sample, b["r"], b["m"], b["G"])
     else:
-        oracle.box_filter(img.astype(np.float64), b["r"], b["w32"].astype(np.float64))
+        oracle.box_filter(sample.astype(np.float64), b["r"], b["w32"].astype(np.float64))
     dt = time.perf_counter() - t0
+    H, W = sample.shape[:2]
     return {"value": round(H * W / dt / 1e9, 5), "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
-            "sample": "one full %dx%d %s image, sigma=%g K=%d, FP64 direct box sums (%.1f s)" %
-                      (H, W, dtype, sigma, K, dt)}
+            "sample": "first %d rows of the %s workload image (%dx%d), sigma=%g K=%d, FP64 direct box sums, "
+                      "%.1f s" % (rows, dtype, H, W, sigma, K, dt)}
 
 
 def sampled_parity(img, out, dtype, sigma, K, n=300):
-    """Spot-check the timed output against the oracle (a few hundred points)."""
+    """Spot-check a timed output against the oracle (a few hundred points)."""
     import oracle
     b = oracle.boxes(sigma, K)
     H, W = img.shape[:2]
     rng = np.random.default_rng(7)
     ys, xs = rng.integers(0, H, n), rng.integers(0, W, n)
-    o = out.cpu().numpy() if dtype != "bf16" else None
+    o = from_dev(out, dtype)
     im3 = img[..., None] if img.ndim == 2 else img
     o3 = o[..., None] if o.ndim == 2 else o
     if dtype == "u8":
         ref = oracle.box_filter_u8_points(im3, b["r"], b["m"], b["G"], ys, xs)
         return bool(np.array_equal(o3[ys, xs, 0], ref))
-    ref = oracle.box_filter_points(im3.astype(np.float64), b["r"], b["w32"].astype(np.float64), ys, xs)
-    return float(np.max(np.abs(o3[ys, xs, 0] - ref)) / np.max(np.abs(im3))) <= 1e-5
+    ref = oracle.box_filter_points(decode(im3, dtype), b["r"], b["w32"].astype(np.float64), ys, xs)
+    return float(np.max(np.abs(o3[ys, xs, 0].astype(np.float64) - ref)) / np.max(np.abs(im3))) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# further workloads
+# ---------------------------------------------------------------------------
+def sigma_k_grid(imgs, steps):
+    """Gpixel/s and HBM fraction at 4096^2 for sigma in {2, 8, 32}, K in {3, 4, 5}."""
+    out = []
+    for dtype, img in imgs.items():
+        H, W = img.shape[:2]
+        for sigma in (2.0, 8.0, 32.0):
+            for K in (3, 4, 5):
+                ms, _ = time_image(img, dtype, sigma, K, steps, 5)
+                out.append({"dtype": dtype, "sigma": sigma, "K": K, "ms": round(ms, 5),
+                            "gpix_s": round(H * W / (ms * 1e-3) / 1e9, 2),
+                            "hbm_frac": roofline(dtype, H, W, 1, ms)["frac"]})
+    return out
+
+
+def batch_workload(steps):
+    """256 three-channel uint8 images (sides 64..2048, sigma log-uniform in
+    [1, 30], K = 4) in one persistent launch, against the same images
+    filtered with one launch each."""
+    import torch
+    import paper_1107_4958_amd as rsg
+    import synthimg
+    specs = synthimg.batch_specs(256)
+    srcs = [to_dev(synthimg.crop_pool(s["H"], s["W"], s["C"], "u8", s["seed"]), "u8") for s in specs]
+    dsts = [torch.empty_like(s) for s in srcs]
+    sig = [s["sigma"] for s in specs]
+    Ks = [s["K"] for s in specs]
+    ws = rsg.filter_batch_tensors(srcs, dsts, sig, Ks)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        rsg.filter_batch_tensors(srcs, dsts, sig, Ks, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(steps):
+        for s, d, sg, k in zip(srcs, dsts, sig, Ks):
+            rsg.filter_tensor(s, sg, k, out=d)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / steps
+    px = sum(s["H"] * s["W"] for s in specs)
+    byt = 2 * sum(s["H"] * s["W"] * s["C"] for s in specs)
+    return {"images": len(specs), "pixels": px, "ms_per_batch": round(ms_batch, 4),
+            "gpix_s": round(px / (ms_batch * 1e-3) / 1e9, 2),
+            "hbm_frac": round(byt / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "ms_one_launch_per_image": round(ms_single, 4),
+            "speedup_vs_one_launch_per_image": round(ms_single / ms_batch, 2)}
+
+
+def precision_workload(steps, npts=8000):
+    """8192^2 single-channel image in uint8 (exact integer sums), FP16 and
+    BF16 storage (FP32 accumulation) and FP32; sigma in {4, 64}, K = 5.
+    NRMS error against the FP64 oracle of the same boxes on sampled points."""
+    import oracle
+    import synthimg
+    H = W = 8192
+    x = synthimg.one_over_f(H, W, 11)
+    forms = {dt: synthimg.to_dtype(x, dt) for dt in ("u8", "f16", "bf16", "f32")}
+    del x
+    rng = np.random.default_rng(5)
+    ys, xs = rng.integers(0, H, npts), rng.integers(0, W, npts)
+    out = []
+    for sigma in (4.0, 64.0):
+        b = oracle.boxes(sigma, 5)
+        for dtype, img in forms.items():
+            ms, res = time_image(img, dtype, sigma, 5, steps, 3, min_pool_bytes=1 << 30)
+            o = from_dev(res, dtype)[ys, xs]
+            im3 = decode(img, dtype)[..., None]
+            ref = oracle.box_filter_points(im3, b["r"], b["w"], ys, xs)     # FP64 weights
+            rec = {"dtype": dtype, "sigma": sigma, "K": 5, "ms": round(ms, 4),
+                   "gpix_s": round(H * W / (ms * 1e-3) / 1e9, 2),
+                   "hbm_frac": roofline(dtype, H, W, 1, ms)["frac"],
+                   "nrms_vs_fp64": float("%.3g" % oracle.nrms(decode(o, dtype), ref))}
+            if dtype == "u8":
+                exact = oracle.box_filter_u8_points(img[..., None], b["r"], b["m"], b["G"], ys, xs)
+                rec["bit_exact_vs_integer_oracle"] = bool(np.array_equal(o, exact))
+            out.append(rec)
+    return out
+
+
+def serving_workload(n=400, qps=1500.0):
+    """Poisson request stream (sides uniform in [128, 4096], C in {1, 3},
+    uint8 or FP32, sigma log-uniform in [0.5, 50], K in {3, 5}) served with
+    continuous batching under an HBM budget.  Sources are windows of
+    device-resident 4096^2 images (row stride = the resident image's);
+    outputs are preallocated.  Latency = done - submit per request."""
+    import torch
+    import paper_1107_4958_amd as rsg
+    import synthimg
+    reqs = synthimg.request_stream(n, qps)
+    fields = [synthimg.one_over_f(4096, 4096, 48 + c) for c in range(3)]
+    resident = {}
+    for dt in ("u8", "f32"):
+        for C in (1, 3):
+            resident[(dt, C)] = to_dev(np.stack([synthimg.to_dtype(f, dt) for f in fields[:C]], axis=-1), dt)
+    del fields
+    dsts = []
+    descs = []
+    for r in reqs:
+        src = resident[(r["dtype"], r["C"])]
+        dst = torch.empty((r["H"], r["W"], r["C"]), dtype=src.dtype, device="cuda")
+        d = rsg.rsg_image_desc()
+        d.src, d.dst = src.data_ptr(), dst.data_ptr()
+        d.H, d.W, d.C = r["H"], r["W"], r["C"]
+        d.src_stride, d.dst_stride = 4096 * r["C"], 0
+        d.dt = rsg.tensor_dtype_code(src)
+        d.sigma, d.K, d.b = r["sigma"], r["K"], rsg.RSG_REPLICATE
+        dsts.append(dst)
+        descs.append(d)
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    cfg = rsg.rsg_server_config()
+    cfg.d_arena, cfg.arena_bytes = arena.data_ptr(), arena.numel()
+    cfg.hbm_budget = 16 << 30
+    cfg.max_inflight, cfg.n_streams, cfg.queue_depth, cfg.max_batch = 8, 4, 1024, 16
+    srv = rsg.rsg_server_create(cfg)
+    tickets = {}
+    stats = {}
+    busy = 0
+    try:
+        t0 = time.perf_counter()
+        i = 0
+        while len(stats) < n:
+            now = time.perf_counter() - t0
+            while i < n and reqs[i]["t_arrive"] <= now:
+                try:
+                    tickets[rsg.rsg_submit(srv, descs[i])] = i
+                    i += 1
+                except rsg.RsgError as e:
+                    if e.code != rsg.RSG_EBUSY:
+                        raise
+                    busy += 1
+                    break
+            for t in [t for t in tickets if tickets[t] not in stats]:
+                st = rsg.rsg_poll(srv, t)
+                if st.done:
+                    stats[tickets[t]] = (st.status, st.t_submit_ns, st.t_done_ns)
+            if now > 120:
+                raise RuntimeError("serving run did not finish in 120 s")
+    finally:
+        rsg.rsg_server_destroy(srv)
+    lat = np.array([(v[2] - v[1]) * 1e-6 for v in stats.values()])
+    assert all(v[0] == rsg.RSG_OK for v in stats.values())
+    span = (max(v[2] for v in stats.values()) - min(v[1] for v in stats.values())) * 1e-9
+    px = sum(r["H"] * r["W"] for r in reqs)
+    return {"requests": n, "qps_offered": qps, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "gpix_s": round(px / span / 1e9, 2),
+            "ebusy_retries": busy, "max_inflight_launches": cfg.max_inflight, "max_batch": cfg.max_batch}
 
 
 def main():
@@ -161,6 +330,7 @@ def main():
     ap.add_argument("--sigma", type=float, default=8.0)
     ap.add_argument("--K", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "u8", "f16", "bf16"])
+    ap.add_argument("--quick", action="store_true", help="headline and its uint8 form only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="first run 3 plain device copies of MIB MiB (a known-size reference for HBM counters)")
@@ -175,6 +345,7 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     import paper_1107_4958_amd  # noqa: F401  (fails loudly if the HIP library is missing)
+    import synthimg
 
     if args.copy_ref:
         a = torch.empty(args.copy_ref << 18, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -185,7 +356,8 @@ def main():
         del a, b
 
     H = W = args.size
-    ms, img, out, _ = time_single(args.dtype, H, W, 1, args.sigma, args.K, args.steps, args.warmup)
+    img = synthimg.image(H, W, 1, args.dtype, 2)
+    ms, out = time_image(img, args.dtype, args.sigma, args.K, args.steps, args.warmup)
     gpx = H * W / (ms * 1e-3) / 1e9
     key = "%s_%dx%d_s%g_K%d" % (args.dtype, H, W, args.sigma, args.K)
     result = {
@@ -200,23 +372,35 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.dtype,
-        "data": "synthetic (seeded 1/f-spectrum image)",
+        "data": "synthetic (seeded 1/f-spectrum image scaled to [0, 255])",
         "config": {"workload": "%dx%d single-channel %s 1/f image, sigma=%g, K=%d constant boxes, replicate "
                                "boundary, one fused kernel launch per step" % (H, W, args.dtype, args.sigma, args.K),
                    "H": H, "W": W, "C": 1, "sigma": args.sigma, "K": args.K},
         "roofline": roofline(args.dtype, H, W, 1, ms, traffic_record(key)),
         "parity_spot_check": sampled_parity(img, out, args.dtype, args.sigma, args.K),
     }
-    # the uint8 form of the same configuration (exact integer path)
-    if args.dtype != "u8":
-        ms8, img8, out8, _ = time_single("u8", H, W, 1, args.sigma, args.K, args.steps, args.warmup)
+    imgs = {args.dtype: img}
+    if args.dtype != "u8":          # the uint8 form of the same configuration (exact integer path)
+        img8 = synthimg.image(H, W, 1, "u8", 2)
+        imgs["u8"] = img8
+        ms8, out8 = time_image(img8, "u8", args.sigma, args.K, args.steps, args.warmup)
         result["u8_variant"] = {"value": round(H * W / (ms8 * 1e-3) / 1e9, 2), "unit": "Gpixel/s",
                                 "ms_per_step": round(ms8, 5),
                                 "roofline": roofline("u8", H, W, 1, ms8,
                                                      traffic_record("u8_%dx%d_s%g_K%d" % (H, W, args.sigma, args.K))),
                                 "parity_spot_check": sampled_parity(img8, out8, "u8", args.sigma, args.K)}
+    if not args.quick:
+        print("bench: sigma x K grid", file=sys.stderr, flush=True)
+        result["sigma_K_grid_4096"] = sigma_k_grid(imgs, max(20, args.steps // 4))
+        print("bench: batch", file=sys.stderr, flush=True)
+        result["batch"] = batch_workload(5)
+        print("bench: precision", file=sys.stderr, flush=True)
+        result["precision_8192"] = precision_workload(10)
+        print("bench: serving", file=sys.stderr, flush=True)
+        result["serving"] = serving_workload()
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(args.dtype, H, W, args.sigma, args.K)
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(img, args.dtype, args.sigma, args.K, rows=min(H, 1024))
     print(json.dumps(result), flush=True)
 
 

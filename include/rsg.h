@@ -179,6 +179,28 @@ int rsg_poll(rsg_server* s, uint64_t ticket, rsg_req_stats* out);
  * arena stays the caller's. */
 int rsg_server_destroy(rsg_server* s);
 
+/* ---------------------------------------------------------------------- */
+/* Tile planning and tuning.                                               */
+/* ---------------------------------------------------------------------- */
+/* The tile plan rsg_gauss_filter / rsg_filter_batch would use for *d: the
+ * segment height (output rows per task; every task covers 64 consecutive
+ * samples of a row and streams 2R + 1 extra rows above its segment), the
+ * number of tasks and the LDS bytes per task.  Host-only: d->src and d->dst
+ * are compared but never dereferenced.  Segment heights come from the tuning
+ * table named by the environment variable RSG_TUNE_TABLE (read once, lines
+ * "dtype C rlo rhi nlo nhi hs", with R the largest box half-width and n the
+ * number of 64-sample strips times H), else from a built-in rule; the plan
+ * never depends on other images of a batch.  Any output pointer may be NULL.
+ * Errors: as rsg_gauss_filter. */
+int rsg_plan_shape(const rsg_image_desc* d, int32_t* seg_height, int32_t* tasks, uint32_t* lds_bytes);
+
+/* Process-wide segment height used instead of the table and the built-in
+ * rule (0 restores them); heights above H are clamped, and every result is
+ * the same for any height up to FP32 rounding (bit-identical for uint8).
+ * For the autotuner: it changes the plan of every later call on every
+ * thread.  Errors: RSG_EINVAL (negative). */
+int rsg_tune_override(int32_t seg_height);
+
 /* Message for the last failure on the calling thread ("" if none). */
 const char* rsg_last_error(void);
 

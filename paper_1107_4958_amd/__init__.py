@@ -8,9 +8,12 @@ fallback path.
 
 Entry points carry the C names (``rsg_fit_boxes``, ``rsg_gauss_filter``,
 ``rsg_filter_batch_workspace``, ``rsg_filter_batch``, ``rsg_server_create``,
-``rsg_submit``, ``rsg_poll``, ``rsg_server_destroy``, ``rsg_last_error``);
-``filter_tensor`` / ``filter_batch_tensors`` / ``Server`` wrap them for torch
-tensors.
+``rsg_submit``, ``rsg_poll``, ``rsg_server_destroy``, ``rsg_plan_shape``,
+``rsg_tune_override``, ``rsg_last_error``); ``filter_tensor`` and
+``filter_batch_tensors`` wrap them for torch tensors.
+
+Unless ``RSG_TUNE_TABLE`` is already set, the library reads the segment
+heights measured by ``autotune.py`` from ``tune_gfx950.txt`` beside it.
 """
 from __future__ import annotations
 
@@ -19,6 +22,9 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librsg.so")
+TUNE_TABLE = os.path.join(_HERE, "tune_gfx950.txt")
+if os.path.exists(TUNE_TABLE):
+    os.environ.setdefault("RSG_TUNE_TABLE", TUNE_TABLE)
 
 RSG_OK = 0
 RSG_EINVAL = -1
@@ -98,10 +104,21 @@ class rsg_req_stats(ctypes.Structure):
 
 
 SYMBOLS = ("rsg_fit_boxes", "rsg_gauss_filter", "rsg_filter_batch_workspace", "rsg_filter_batch",
-           "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_last_error")
+           "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_plan_shape",
+           "rsg_tune_override", "rsg_last_error")
 
 
 def _load():
+    # One HIP runtime per process: torch ships its own copy of the HIP and HSA
+    # runtimes (same sonames as /opt/rocm's).  Loading torch first makes
+    # librsg.so bind to that copy, so the device pointers and stream handles
+    # torch hands over belong to the runtime the library launches on; loaded
+    # the other way round, a process holds two runtimes and the second may see
+    # no device at all.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("librsg.so is not built (run paper_1107_4958_amd.build.build()); "
                           "there is no non-HIP fallback")
@@ -115,6 +132,9 @@ def _load():
     lib.rsg_submit.argtypes = [V, ctypes.POINTER(rsg_image_desc), ctypes.POINTER(ctypes.c_uint64)]
     lib.rsg_poll.argtypes = [V, ctypes.c_uint64, ctypes.POINTER(rsg_req_stats)]
     lib.rsg_server_destroy.argtypes = [V]
+    lib.rsg_plan_shape.argtypes = [ctypes.POINTER(rsg_image_desc), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32)]
+    lib.rsg_tune_override.argtypes = [ctypes.c_int32]
     lib.rsg_last_error.argtypes = []
     lib.rsg_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS[:-1]:
@@ -194,6 +214,17 @@ def rsg_poll(server: int, ticket: int) -> rsg_req_stats:
 
 def rsg_server_destroy(server: int) -> None:
     _check(_lib.rsg_server_destroy(ctypes.c_void_p(server)))
+
+
+def rsg_plan_shape(desc: rsg_image_desc):
+    """(segment height, tasks, LDS bytes per task) of the plan for `desc`."""
+    hs, nt, lds = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_uint32(0)
+    _check(_lib.rsg_plan_shape(ctypes.byref(desc), ctypes.byref(hs), ctypes.byref(nt), ctypes.byref(lds)))
+    return hs.value, nt.value, lds.value
+
+
+def rsg_tune_override(seg_height: int) -> None:
+    _check(_lib.rsg_tune_override(int(seg_height)))
 
 
 # ---------------------------------------------------------------------------

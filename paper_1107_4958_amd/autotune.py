@@ -1,0 +1,165 @@
+"""Measure the fastest segment height per tuning bucket on the device and
+write the table the planner reads.
+
+    python -m paper_1107_4958_amd.autotune [--out PATH] [--quick]
+
+A task of the fused kernel covers 64 consecutive samples of a row and a
+segment of hs output rows, streaming 2R + 1 extra rows above the segment
+(R: largest box half-width).  Short segments give many tasks but re-read
+the halo often; long ones give few tasks.  The best hs depends on the
+element type, the channel count, R and the amount of work (strips x rows),
+so the table is keyed on exactly those: lines "dtype C rlo rhi nlo nhi hs".
+
+For every (dtype, C, image side, sigma, K) point the script times each
+candidate height through rsg_tune_override on rotating synthetic images
+resident in HBM (timed with HIP events on the launch stream) and keeps the
+fastest.  Points are then turned into buckets: R ranges split halfway
+between measured R values, work ranges split at the geometric middle
+between measured sizes.  BF16 shares the FP16 lines (same element size and
+kernel structure).
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tune_gfx950.txt")
+
+CANDIDATES = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048)
+POINTS = ((1.0, 3), (2.0, 3), (4.0, 5), (8.0, 3), (16.0, 4), (32.0, 5), (64.0, 5))
+SIDES = (512, 1024, 2048, 4096, 8192)
+MAX_SAMPLES = 8192 * 8192          # per image (side^2 * C)
+POOL_BYTES = 640 << 20             # rotate through more than the last-level cache
+
+
+def _torch_dtype(torch, dt):
+    return {"u8": torch.uint8, "f32": torch.float32, "f16": torch.float16}[dt]
+
+
+def _time_config(rsg, torch, dt, side, C, sigma, K, reps):
+    """{hs: microseconds} for every candidate height the planner accepts."""
+    shape = (side, side, C) if C > 1 else (side, side)
+    tdt = _torch_dtype(torch, dt)
+    if dt == "u8":
+        base = torch.randint(0, 256, shape, dtype=torch.uint8, device="cuda")
+    else:
+        base = (torch.rand(shape, device="cuda") * 255).to(tdt)
+    nbytes = 2 * base.numel() * base.element_size()
+    npairs = max(2, min(8, math.ceil(POOL_BYTES / nbytes)))
+    srcs = [base] + [base.clone() for _ in range(npairs - 1)]
+    dsts = [torch.empty_like(base) for _ in range(npairs)]
+    stream = torch.cuda.current_stream()
+    code = rsg.tensor_dtype_code(base)
+    out = {}
+    for hs in (0,) + tuple(h for h in CANDIDATES if h <= side):
+        rsg.rsg_tune_override(hs)
+        try:
+            d = rsg.make_desc(srcs[0], dsts[0], sigma, K)
+            plan_hs = rsg.rsg_plan_shape(d)[0]
+        except rsg.RsgError:
+            continue
+        if hs and plan_hs != hs:
+            continue                                  # clamped to another candidate
+
+        def launch(i):
+            rsg.rsg_gauss_filter(srcs[i % npairs].data_ptr(), dsts[i % npairs].data_ptr(), side, side, C, code,
+                                 sigma, K, rsg.RSG_REPLICATE, stream.cuda_stream)
+
+        for i in range(3):
+            launch(i)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(reps):
+            launch(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[hs if hs else -plan_hs] = e0.elapsed_time(e1) / reps * 1000.0
+    rsg.rsg_tune_override(0)
+    del srcs, dsts, base
+    return out
+
+
+def _buckets(values, log=False):
+    """Ranges [lo, hi] covering all integers, split between sorted values."""
+    v = sorted(set(values))
+    cuts = []
+    for a, b in zip(v, v[1:]):
+        cuts.append(int(math.sqrt(a * b)) if log else (a + b) // 2)
+    los = [0] + [c + 1 for c in cuts]
+    his = cuts + [2 ** 62 if log else 1 << 30]
+    return dict(zip(v, zip(los, his)))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--quick", action="store_true", help="fewer sides and points (a smoke run)")
+    ap.add_argument("--dtypes", default="u8,f32,f16")
+    ap.add_argument("--channels", default="1,2,3,4")
+    args = ap.parse_args(argv)
+
+    os.environ["RSG_TUNE_TABLE"] = ""                 # measure against the built-in rule, not an old table
+    import torch
+    if not torch.cuda.is_available():
+        print("autotune needs a GPU", file=sys.stderr)
+        return 1
+    sys.path.insert(0, os.path.dirname(HERE))
+    import paper_1107_4958_amd as rsg
+
+    sides = SIDES[1::2] if args.quick else SIDES
+    points = POINTS[::3] if args.quick else POINTS
+    rows = []
+    t_start = time.time()
+    for dt in args.dtypes.split(","):
+        for C in (int(c) for c in args.channels.split(",")):
+            for side in sides:
+                if side * side * C > MAX_SAMPLES:
+                    continue
+                for sigma, K in points:
+                    R = int(max(rsg.rsg_fit_boxes(sigma, K).r[:K]))
+                    reps = 10 if side * side * C >= 4096 * 4096 else 30
+                    res = _time_config(rsg, torch, dt, side, C, sigma, K, reps)
+                    if not res:
+                        continue
+                    default = [v for k, v in res.items() if k < 0]
+                    tuned = {k: v for k, v in res.items() if k > 0}
+                    best = min(tuned, key=tuned.get)
+                    n = -(-side * C // 64) * side
+                    rows.append(dict(dt=dt, C=C, R=R, n=n, hs=best, us=tuned[best],
+                                     default_us=default[0] if default else float("nan"),
+                                     side=side, sigma=sigma, K=K))
+                    print("%-4s C=%d side=%5d sigma=%5.1f K=%d R=%3d: best hs=%4d %8.1f us (built-in rule %8.1f us)"
+                          % (dt, C, side, sigma, K, R, best, tuned[best], rows[-1]["default_us"]), flush=True)
+
+    code = {"u8": 0, "f32": 1, "f16": 2, "bf16": 3}
+    lines = ["# segment heights measured by paper_1107_4958_amd/autotune.py on %s (%.0f s)"
+             % (torch.cuda.get_device_name(0), time.time() - t_start),
+             "# dtype C rlo rhi nlo nhi hs   # measured point: side sigma K, best / built-in-rule microseconds"]
+    for dt in sorted({r["dt"] for r in rows}, key=code.get):
+        for C in sorted({r["C"] for r in rows if r["dt"] == dt}):
+            pts = [r for r in rows if r["dt"] == dt and r["C"] == C]
+            nb = _buckets([r["n"] for r in pts], log=True)
+            for n in sorted(nb):
+                at_n = [r for r in pts if r["n"] == n]
+                rb = _buckets([r["R"] for r in at_n])
+                for R in sorted(rb):
+                    r = min((x for x in at_n if x["R"] == R), key=lambda x: x["us"])
+                    for dcode in ((code["f16"], code["bf16"]) if dt == "f16" else (code[dt],)):
+                        lines.append("%d %d %d %d %d %d %d   # %d %g %d: %.1f / %.1f" % (
+                            dcode, C, rb[R][0], rb[R][1], nb[n][0], nb[n][1], r["hs"],
+                            r["side"], r["sigma"], r["K"], r["us"], r["default_us"]))
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote %d lines to %s" % (len(lines) - 2, args.out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

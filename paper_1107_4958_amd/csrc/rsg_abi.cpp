@@ -58,6 +58,27 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
 
 extern "C" {
 
+int rsg_plan_shape(const rsg_image_desc* d, int32_t* seg_height, int32_t* tasks, uint32_t* lds_bytes)
+{
+    using namespace rsg;
+    if (!d) return set_error(RSG_EINVAL, "rsg_plan_shape: NULL descriptor");
+    ImgParams ip;
+    const int rc = plan_image(*d, &ip);
+    if (rc != RSG_OK) return rc;
+    if (seg_height) *seg_height = ip.hs;
+    if (tasks) *tasks = ip.ntasks;
+    if (lds_bytes) *lds_bytes = ip.lds_bytes;
+    return RSG_OK;
+}
+
+int rsg_tune_override(int32_t seg_height)
+{
+    using namespace rsg;
+    if (seg_height < 0) return set_error(RSG_EINVAL, "segment height must be >= 0");
+    set_hs_override(seg_height);
+    return RSG_OK;
+}
+
 int rsg_fit_boxes(double sigma, int K, rsg_boxes* out)
 {
     return rsg::make_boxes(sigma, K, true, out);

@@ -66,6 +66,8 @@ struct BatchTask {
 
 // Plan for one image: validates, fits (cached), picks the tile shape.
 int plan_image(const rsg_image_desc& d, ImgParams* ip);
+// Process-wide segment height that overrides the tuning table (0: none).
+void set_hs_override(int hs);
 
 // Launchers (rsg_kernels.hip).
 int launch_single(const ImgParams& ip, hipStream_t stream);

@@ -5,11 +5,13 @@
 // The choice is a pure function of the image's own parameters (dtype, C, H,
 // W, the box half-widths, boundary, pointer alignment), never of the batch it
 // arrives in, so an image filters to the same bits alone or in a mix.  Shapes
-// come from a tuning table (tile-shape buckets measured on the device, see
-// autotune.py) when one is loaded, otherwise from the built-in rule below.
+// come from a tuning table (segment heights measured on the device by the
+// package's autotune.py) when one is loaded, otherwise from the built-in rule
+// below.
 #include "rsg_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -29,12 +31,15 @@ constexpr uint32_t kLdsLimit = 160u * 1024u;    // gfx950: 160 KiB of LDS per CU
 int gcd_i(int a, int b) { while (b) { int t = a % b; a = b; b = t; } return a; }
 int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
 
-// Tuning table (text): lines "dtype C rlo rhi hs", '#' starts a comment.
-// The segment height of an image whose largest half-width R lies in
-// [rlo, rhi] is taken from the first matching line.
-struct TuneEntry { int dtype, C, rlo, rhi, hs; };
+// Tuning table (text): lines "dtype C rlo rhi nlo nhi hs", '#' starts a
+// comment.  An image of dtype and channel count C whose largest half-width R
+// lies in [rlo, rhi] and whose work size n = strips * H (strips of 64
+// samples) lies in [nlo, nhi] takes segment height hs from the first
+// matching line.
+struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs; };
 std::once_flag g_tune_once;
 std::vector<TuneEntry> g_tune;
+std::atomic<int> g_hs_override{0};
 
 void load_tune_table()
 {
@@ -47,15 +52,20 @@ void load_tune_table()
         if (h != std::string::npos) line.resize(h);
         std::istringstream is(line);
         TuneEntry e;
-        if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.hs && e.hs > 0) g_tune.push_back(e);
+        if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.nlo >> e.nhi >> e.hs && e.hs > 0) g_tune.push_back(e);
     }
 }
 
-bool tuned_hs(int dtype, int C, int R, int* hs)
+bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs)
 {
+    const int ov = g_hs_override.load(std::memory_order_relaxed);
+    if (ov > 0) { *hs = ov; return true; }
     std::call_once(g_tune_once, load_tune_table);
     for (const auto& e : g_tune)
-        if (e.dtype == dtype && e.C == C && R >= e.rlo && R <= e.rhi) { *hs = e.hs; return true; }
+        if (e.dtype == dtype && e.C == C && R >= e.rlo && R <= e.rhi && n >= e.nlo && n <= e.nhi) {
+            *hs = e.hs;
+            return true;
+        }
     return false;
 }
 
@@ -79,6 +89,8 @@ int default_hs(int H, int nstrips, int R, uint32_t lds)
 }
 
 }  // namespace
+
+void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_order_relaxed); }
 
 int plan_image(const rsg_image_desc& d, ImgParams* ip)
 {
@@ -179,7 +191,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
 
     // ---- segment height ----
     int hs = 0;
-    if (!tuned_hs(d.dt, C, R, &hs)) hs = default_hs(d.H, p.nstrips, R, p.lds_bytes);
+    if (!tuned_hs(d.dt, C, R, int64_t(p.nstrips) * d.H, &hs)) hs = default_hs(d.H, p.nstrips, R, p.lds_bytes);
     hs = std::max(1, std::min(hs, d.H));
     {   // every offset a task touches (rows ybase .. ybase + its padded
         // iteration count, times the larger stride) must stay below 2^30

@@ -21,7 +21,7 @@ def _rsg():
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "rsg.h")).read()
     declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(rsg_\w+)\s*\(", header, re.M))
-    assert len(declared) == 9
+    assert len(declared) == 11
     rsg = _rsg()
     lib = ctypes.CDLL(rsg.LIB_PATH)
     for name in declared:
@@ -126,3 +126,19 @@ def test_uint8_unsupported_where_no_integer_scale_exists():
     rc = lib.rsg_gauss_filter(ctypes.c_void_p(0x100000), ctypes.c_void_p(0x90000000), 8, 8, 1, rsg.RSG_U8,
                               2000.0, 5, rsg.RSG_REPLICATE, None)
     assert rc == rsg.RSG_EUNSUPPORTED
+
+
+def test_one_hip_runtime_per_process():
+    """The library must bind to the HIP runtime torch already uses (the
+    pointers and streams it receives come from torch), whatever the import
+    order: a fresh process that imports the package first maps exactly one
+    libamdhip64."""
+    import subprocess
+    import sys
+    code = ("import paper_1107_4958_amd, torch\n"
+            "m = {l.split()[-1] for l in open('/proc/self/maps').read().splitlines() if 'libamdhip64' in l}\n"
+            "print(len(m))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         env=dict(os.environ, PYTHONPATH=ROOT))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"

@@ -146,3 +146,18 @@ def test_at_scale_4096(dtype, sigma, K):
 @pytest.mark.parametrize("sigma", [4.0, 64.0])
 def test_precision_8192(dtype, sigma):
     _sampled_check(8192, 8192, 1, dtype, sigma, 5, npts=500, seed=4)
+
+
+@pytest.mark.parametrize("dtype,H,W,C,sigma,K", [("u8", 300, 517, 3, 5.0, 4), ("f32", 700, 300, 1, 12.0, 5),
+                                                 ("u8", 90, 1100, 1, 30.0, 3)])
+def test_any_segment_height_gives_the_oracle(dtype, H, W, C, sigma, K):
+    """The segment height only changes how rows are split into tasks: every
+    height (1, ragged, one task per strip) must match the oracle."""
+    import paper_1107_4958_amd as rsg
+    img = synthimg.image(H, W, C, dtype, 31)
+    try:
+        for hs in (1, 7, 64, 333, 100000):
+            rsg.rsg_tune_override(hs)
+            _check(img, dtype, sigma, K, oracle.REPLICATE)
+    finally:
+        rsg.rsg_tune_override(0)

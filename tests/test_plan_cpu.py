@@ -1,0 +1,71 @@
+"""Host-side tile planning through the C ABI (no device needed): the plan
+query, the tuning-table lookup and the process-wide override."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import paper_1107_4958_amd as rsg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _desc(H, W, C=1, dt=rsg.RSG_F32, sigma=8.0, K=3, stride=0):
+    d = rsg.rsg_image_desc()
+    d.src, d.dst = 0x10000, 0x100000000000       # distinct ranges; never dereferenced
+    d.H, d.W, d.C = H, W, C
+    d.src_stride = d.dst_stride = stride
+    d.dt, d.sigma, d.K, d.b = dt, sigma, K, rsg.RSG_REPLICATE
+    return d
+
+
+def test_plan_shape_basics():
+    hs, tasks, lds = rsg.rsg_plan_shape(_desc(4096, 4096))
+    assert 1 <= hs <= 4096 and lds > 0
+    assert tasks == 64 * -(-4096 // hs)             # 64-sample strips x segments
+    hs3, tasks3, _ = rsg.rsg_plan_shape(_desc(100, 70, C=3, dt=rsg.RSG_U8))
+    assert tasks3 == -(-210 // 64) * -(-100 // hs3)
+
+
+def test_override_and_clamp():
+    try:
+        rsg.rsg_tune_override(200)
+        assert rsg.rsg_plan_shape(_desc(4096, 4096))[0] == 200
+        assert rsg.rsg_plan_shape(_desc(150, 4096))[0] == 150      # clamped to H
+        with pytest.raises(rsg.RsgError):
+            rsg.rsg_tune_override(-1)
+    finally:
+        rsg.rsg_tune_override(0)
+
+
+def test_huge_stride_shrinks_segments_or_is_refused():
+    """Every offset a task touches must stay below 2^30 bytes: a wide stride
+    makes the planner shorten segments, an absurd one is refused."""
+    hs, _, _ = rsg.rsg_plan_shape(_desc(4096, 64, stride=1 << 20))
+    assert hs * (1 << 22) < (1 << 30)
+    with pytest.raises(rsg.RsgError) as e:
+        rsg.rsg_plan_shape(_desc(64, 64, sigma=30.0, stride=1 << 26))
+    assert e.value.code == rsg.RSG_EUNSUPPORTED
+
+
+def test_tuning_table_lookup(tmp_path):
+    """A table line applies only inside its (dtype, C, R, work) bucket."""
+    R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
+    n = 64 * 4096
+    table = tmp_path / "t.txt"
+    table.write_text("# comment\n1 1 %d %d %d %d 96\n0 1 0 1000 0 %d 40  # other dtype\n" % (R, R, n, n, 1 << 40))
+    code = ("import paper_1107_4958_amd as r, sys; sys.path.insert(0, %r)\n"
+            "from test_plan_cpu import _desc\n"
+            "print(r.rsg_plan_shape(_desc(4096, 4096))[0], r.rsg_plan_shape(_desc(4096, 2048))[0],"
+            " r.rsg_plan_shape(_desc(4096, 4096, dt=r.RSG_U8))[0], r.rsg_plan_shape(_desc(4096, 4096, sigma=2.0))[0])"
+            % os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, RSG_TUNE_TABLE=str(table), PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    a, b, c, d = map(int, out.stdout.split())
+    assert a == 96                 # inside the bucket
+    assert b == rsg.rsg_plan_shape(_desc(4096, 2048))[0]   # work size outside the line: built-in rule
+    assert c == 40                 # uint8 line
+    default = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=2.0))[0]
+    assert d == default            # R outside the line's range: built-in rule
