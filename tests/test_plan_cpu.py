@@ -49,23 +49,30 @@ def test_huge_stride_shrinks_segments_or_is_refused():
     assert e.value.code == rsg.RSG_EUNSUPPORTED
 
 
-def test_tuning_table_lookup(tmp_path):
-    """A table line applies only inside its (dtype, C, R, work) bucket."""
-    R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
-    n = 64 * 4096
-    table = tmp_path / "t.txt"
-    table.write_text("# comment\n1 1 %d %d %d %d 96\n0 1 0 1000 0 %d 40  # other dtype\n" % (R, R, n, n, 1 << 40))
+def _plans_with_table(path):
     code = ("import paper_1107_4958_amd as r, sys; sys.path.insert(0, %r)\n"
             "from test_plan_cpu import _desc\n"
             "print(r.rsg_plan_shape(_desc(4096, 4096))[0], r.rsg_plan_shape(_desc(4096, 2048))[0],"
             " r.rsg_plan_shape(_desc(4096, 4096, dt=r.RSG_U8))[0], r.rsg_plan_shape(_desc(4096, 4096, sigma=2.0))[0])"
             % os.path.dirname(os.path.abspath(__file__)))
-    env = dict(os.environ, RSG_TUNE_TABLE=str(table), PYTHONPATH=ROOT)
-    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    env = dict(os.environ, RSG_TUNE_TABLE=str(path), PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
-    a, b, c, d = map(int, out.stdout.split())
+    return list(map(int, out.stdout.split()))
+
+
+def test_tuning_table_lookup(tmp_path):
+    """A table line applies only inside its (dtype, C, R, work) bucket;
+    outside every line the built-in rule decides."""
+    R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
+    n = 64 * 4096
+    table = tmp_path / "t.txt"
+    table.write_text("# comment\n1 1 %d %d %d %d 96\n0 1 0 1000 0 %d 40  # other dtype\n" % (R, R, n, n, 1 << 40))
+    empty = tmp_path / "empty.txt"
+    empty.write_text("")
+    a, b, c, d = _plans_with_table(table)
+    _, b0, _, d0 = _plans_with_table(empty)
     assert a == 96                 # inside the bucket
-    assert b == rsg.rsg_plan_shape(_desc(4096, 2048))[0]   # work size outside the line: built-in rule
+    assert b == b0                 # work size outside the line: built-in rule
     assert c == 40                 # uint8 line
-    default = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=2.0))[0]
-    assert d == default            # R outside the line's range: built-in rule
+    assert d == d0                 # R outside the line's range: built-in rule
