@@ -185,7 +185,9 @@ int rsg_server_destroy(rsg_server* s);
 /* The tile plan rsg_gauss_filter / rsg_filter_batch would use for *d: the
  * segment height (output rows per task; every task covers 64 consecutive
  * samples of a row and streams 2R + 1 extra rows above its segment), the
- * number of tasks and the LDS bytes per task.  Host-only: d->src and d->dst
+ * number of tasks and the LDS bytes per task.  For an image planned on the
+ * two-pass path the segment height is H, the tasks are the workgroups of
+ * both passes (16 rows each) and the LDS is the larger pass's.  Host-only: d->src and d->dst
  * are compared but never dereferenced.  Segment heights come from the tuning
  * table named by the environment variable RSG_TUNE_TABLE (read once, lines
  * "dtype C rlo rhi nlo nhi hs", with R the largest box half-width and n the
@@ -200,6 +202,17 @@ int rsg_plan_shape(const rsg_image_desc* d, int32_t* seg_height, int32_t* tasks,
  * For the autotuner: it changes the plan of every later call on every
  * thread.  Errors: RSG_EINVAL (negative). */
 int rsg_tune_override(int32_t seg_height);
+
+/* Process-wide choice of kernel path for every later plan: 0 lets the
+ * planner choose (two passes for wide boxes, R * C >= 40, when they fit),
+ * 1 forces the fused single-launch kernel, 2 forces the two-pass path (row
+ * filter into an FP32 / uint32 intermediate stored transposed, then the same
+ * on the intermediate; the intermediate, 4 H W C bytes, is allocated and
+ * released in stream order).  Results agree to FP32 rounding and are
+ * bit-identical for uint8.  For the autotuner and tests.
+ * Errors: RSG_EINVAL (path not 0, 1 or 2); later plans return
+ * RSG_EUNSUPPORTED when the forced path cannot hold the boxes. */
+int rsg_tune_path(int32_t path);
 
 /* Message for the last failure on the calling thread ("" if none). */
 const char* rsg_last_error(void);

@@ -9,7 +9,7 @@ fallback path.
 Entry points carry the C names (``rsg_fit_boxes``, ``rsg_gauss_filter``,
 ``rsg_filter_batch_workspace``, ``rsg_filter_batch``, ``rsg_server_create``,
 ``rsg_submit``, ``rsg_poll``, ``rsg_server_destroy``, ``rsg_plan_shape``,
-``rsg_tune_override``, ``rsg_last_error``); ``filter_tensor`` and
+``rsg_tune_override``, ``rsg_tune_path``, ``rsg_last_error``); ``filter_tensor`` and
 ``filter_batch_tensors`` wrap them for torch tensors.
 
 Unless ``RSG_TUNE_TABLE`` is already set, the library reads the segment
@@ -105,7 +105,7 @@ class rsg_req_stats(ctypes.Structure):
 
 SYMBOLS = ("rsg_fit_boxes", "rsg_gauss_filter", "rsg_filter_batch_workspace", "rsg_filter_batch",
            "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_plan_shape",
-           "rsg_tune_override", "rsg_last_error")
+           "rsg_tune_override", "rsg_tune_path", "rsg_last_error")
 
 
 def _load():
@@ -135,6 +135,7 @@ def _load():
     lib.rsg_plan_shape.argtypes = [ctypes.POINTER(rsg_image_desc), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32)]
     lib.rsg_tune_override.argtypes = [ctypes.c_int32]
+    lib.rsg_tune_path.argtypes = [ctypes.c_int32]
     lib.rsg_last_error.argtypes = []
     lib.rsg_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS[:-1]:
@@ -225,6 +226,13 @@ def rsg_plan_shape(desc: rsg_image_desc):
 
 def rsg_tune_override(seg_height: int) -> None:
     _check(_lib.rsg_tune_override(int(seg_height)))
+
+
+RSG_PATH_AUTO, RSG_PATH_FUSED, RSG_PATH_TWO_PASS = 0, 1, 2
+
+
+def rsg_tune_path(path: int) -> None:
+    _check(_lib.rsg_tune_path(int(path)))
 
 
 # ---------------------------------------------------------------------------

@@ -37,7 +37,7 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
             std::string msg = g_last_error;
             return set_error(rc, "image %d: %s", i, msg.c_str());
         }
-        total += imgs[i].ntasks;
+        if (imgs[i].path == kPathFused) total += imgs[i].ntasks;
     }
     if (total > (int64_t(1) << 30)) return set_error(RSG_EUNSUPPORTED, "batch too large");
     tasks.reserve(size_t(total));
@@ -50,7 +50,8 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
                int64_t(imgs[b].ntasks) * (imgs[b].hs + 2 * imgs[b].R);
     });
     for (int i : order)
-        for (int t = 0; t < imgs[i].ntasks; ++t) tasks.push_back(BatchTask{i, t});
+        if (imgs[i].path == kPathFused)       // two-pass images are launched on their own
+            for (int t = 0; t < imgs[i].ntasks; ++t) tasks.push_back(BatchTask{i, t});
     return RSG_OK;
 }
 
@@ -68,6 +69,14 @@ int rsg_plan_shape(const rsg_image_desc* d, int32_t* seg_height, int32_t* tasks,
     if (seg_height) *seg_height = ip.hs;
     if (tasks) *tasks = ip.ntasks;
     if (lds_bytes) *lds_bytes = ip.lds_bytes;
+    return RSG_OK;
+}
+
+int rsg_tune_path(int32_t path)
+{
+    using namespace rsg;
+    if (path < 0 || path > 2) return set_error(RSG_EINVAL, "path must be 0 (planner), 1 (fused) or 2 (two-pass)");
+    set_path_override(path);
     return RSG_OK;
 }
 

@@ -190,15 +190,30 @@ __device__ __forceinline__ void load_chunk_elem(Chunk<Tr, NPL>& ch, __amdgpu_buf
 }
 
 // uint8 output: round half up of U / G^2, exactly.  N = U + floor(G^2/2) < 256 G^2.
+__device__ __forceinline__ uint32_t exact_round_div_u(uint64_t U, uint64_t G2, uint64_t G2half, float invG2)
+{
+    const uint64_t N = U + G2half;
+    const float nf = float(uint32_t(N >> 32)) * 4294967296.0f + float(uint32_t(N));
+    uint32_t q = uint32_t(nf * invG2);
+    const uint64_t prod = uint64_t(q) * G2;
+    if (prod > N) q -= 1;
+    else if (N - prod >= G2) q += 1;
+    return q;
+}
 __device__ __forceinline__ uint32_t exact_round_div(uint64_t U, const ImgParams& ip)
 {
-    const uint64_t N = U + ip.G2half;
-    const float nf = float(uint32_t(N >> 32)) * 4294967296.0f + float(uint32_t(N));
-    uint32_t q = uint32_t(nf * ip.invG2);
-    const uint64_t prod = uint64_t(q) * ip.G2;
-    if (prod > N) q -= 1;
-    else if (N - prod >= ip.G2) q += 1;
-    return q;
+    return exact_round_div_u(U, ip.G2, ip.G2half, ip.invG2);
+}
+
+// One element at byte offset `boff` of a buffer, as float.
+template <class Tr>
+__device__ __forceinline__ float Tr_load_one(__amdgpu_buffer_rsrc_t rs, int boff)
+{
+    uint32_t w[1];
+    if constexpr (Tr::kSize == 1) w[0] = __builtin_amdgcn_raw_buffer_load_b8(rs, boff, 0, 0);
+    else if constexpr (Tr::kSize == 2) w[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, boff, 0, 0);
+    else w[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, boff, 0, 0);
+    return float(Tr::unpack(w, 0));
 }
 
 // Orders this wave's LDS writes before its later reads (one-wave groups).

@@ -56,6 +56,35 @@ struct ImgParams {
     int32_t nstrips, nsegs, ntasks;
     int32_t variant;               // kernel instantiation
     uint32_t lds_bytes;            // dynamic LDS per wave
+    // two-pass path (wide boxes): row filter + transposed store, twice
+    int32_t path;                  // kPathFused or kPathTwoPass
+    int32_t pnpl[2];               // samples per lane of pass A, pass B
+    uint32_t plds[2];              // LDS bytes per workgroup of pass A, pass B
+};
+
+constexpr int kPathFused = 0;
+constexpr int kPathTwoPass = 1;
+
+// One pass of the two-pass path: filter `rows` rows of `len` samples (taps C
+// samples apart) and store the result transposed (element (x, row) at
+// dst[x * dst_stride + row]).
+struct PassParams {
+    const void* src;
+    void* dst;
+    int64_t src_stride;            // elements per input row
+    int64_t dst_stride;            // elements per output row (= input row count of the next pass)
+    int32_t rows, len;
+    int32_t R;
+    int32_t r[RSG_MAX_K];
+    float wf[RSG_MAX_K];
+    uint32_t m[RSG_MAX_K];
+    float dc32;
+    uint64_t G2, G2half;
+    float invG2;
+    int32_t boundary;
+    int32_t vec;                   // rows allow 16-byte chunk loads
+    int32_t win_pitch;             // LDS words per wave window
+    int32_t win_shift;             // window start offset (aligns its new part to 16 bytes)
 };
 
 // One unit of work of a batched launch.
@@ -68,6 +97,8 @@ struct BatchTask {
 int plan_image(const rsg_image_desc& d, ImgParams* ip);
 // Process-wide segment height that overrides the tuning table (0: none).
 void set_hs_override(int hs);
+// Process-wide path override (0: planner's choice, 1: fused, 2: two-pass).
+void set_path_override(int path);
 
 // Launchers (rsg_kernels.hip).
 int launch_single(const ImgParams& ip, hipStream_t stream);
@@ -75,6 +106,19 @@ int launch_single_u8(const ImgParams& ip, hipStream_t stream);
 int launch_single_f32(const ImgParams& ip, hipStream_t stream);
 int launch_single_f16(const ImgParams& ip, hipStream_t stream);
 int launch_single_bf16(const ImgParams& ip, hipStream_t stream);
+// Two-pass path: pass A (image -> intermediate) or pass B (intermediate -> image).
+int launch_pass(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
+int launch_pass_u8(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
+int launch_pass_f32(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
+int launch_pass_f16(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
+int launch_pass_bf16(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
+// Window geometry of one pass (shared by the planner and the launcher).
+constexpr int kPassRowsHost = 16;
+inline int pass_win_pitch(int npl, int hw) { return (kWave * npl + hw + 3 + 3) / 4 * 4; }
+inline uint32_t pass_lds_bytes(int npl, int hw)
+{
+    return uint32_t(4 * (kPassRowsHost * pass_win_pitch(npl, hw) + kWave * npl * (kPassRowsHost + 1)));
+}
 // One persistent launch over the tasks of one (dtype, C, kt) class.
 struct BatchClassLaunch {
     int dtype, C, kt;

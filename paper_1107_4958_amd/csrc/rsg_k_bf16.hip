@@ -13,4 +13,9 @@ int launch_batch_class_bf16(const BatchClassLaunch& b, hipStream_t stream)
     return dispatch::launch_batch_t<dev::TrBF16>(b, stream);
 }
 
+int launch_pass_bf16(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream)
+{
+    return dispatch::launch_pass_t<dev::TrBF16>(ip, pass, pp, stream);
+}
+
 }  // namespace rsg

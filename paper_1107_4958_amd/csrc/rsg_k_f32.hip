@@ -13,4 +13,9 @@ int launch_batch_class_f32(const BatchClassLaunch& b, hipStream_t stream)
     return dispatch::launch_batch_t<dev::TrF32>(b, stream);
 }
 
+int launch_pass_f32(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream)
+{
+    return dispatch::launch_pass_t<dev::TrF32>(ip, pass, pp, stream);
+}
+
 }  // namespace rsg

@@ -13,4 +13,9 @@ int launch_batch_class_u8(const BatchClassLaunch& b, hipStream_t stream)
     return dispatch::launch_batch_t<dev::TrU8>(b, stream);
 }
 
+int launch_pass_u8(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream)
+{
+    return dispatch::launch_pass_t<dev::TrU8>(ip, pass, pp, stream);
+}
+
 }  // namespace rsg

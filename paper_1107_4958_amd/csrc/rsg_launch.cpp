@@ -11,8 +11,83 @@
 
 namespace rsg {
 
+int launch_pass(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream)
+{
+    switch (ip.dtype) {
+    case RSG_U8: return launch_pass_u8(ip, pass, pp, stream);
+    case RSG_F32: return launch_pass_f32(ip, pass, pp, stream);
+    case RSG_F16: return launch_pass_f16(ip, pass, pp, stream);
+    case RSG_BF16: return launch_pass_bf16(ip, pass, pp, stream);
+    default: return set_error(RSG_EINVAL, "bad dtype %d", ip.dtype);
+    }
+}
+
+namespace {
+
+PassParams pass_params(const ImgParams& ip, int pass, void* mid)
+{
+    PassParams pp;
+    std::memset(&pp, 0, sizeof(pp));
+    const int es = dtype_size(ip.dtype);
+    const int WC = ip.W * ip.C;
+    const int npl = ip.pnpl[pass];
+    if (pass == 0) {                       // image rows -> intermediate (W*C) x H
+        pp.src = ip.src;
+        pp.dst = mid;
+        pp.src_stride = ip.src_stride;
+        pp.dst_stride = ip.H;
+        pp.rows = ip.H;
+        pp.len = WC;
+        // chunk loads use the widest of 16 / 8 / 4 bytes that divides the chunk
+        const int cb = npl * es;
+        const int g = cb % 16 == 0 ? 16 : (cb % 8 == 0 ? 8 : (cb % 4 == 0 ? 4 : 0));
+        const uintptr_t a = reinterpret_cast<uintptr_t>(ip.src);
+        pp.vec = g > 0 && a % g == 0 && (ip.src_stride * es) % g == 0;
+    } else {                               // intermediate rows (image columns) -> image
+        pp.src = mid;
+        pp.dst = ip.dst;
+        pp.src_stride = ip.H;
+        pp.dst_stride = ip.dst_stride;
+        pp.rows = WC;
+        pp.len = ip.H;
+        pp.vec = (int64_t(ip.H) * 4) % 16 == 0;
+    }
+    pp.R = ip.R;
+    for (int k = 0; k < RSG_MAX_K; ++k) {
+        pp.r[k] = ip.r[k];
+        pp.wf[k] = ip.wf[k];
+        pp.m[k] = ip.m[k];
+    }
+    pp.dc32 = ip.dc32;
+    pp.G2 = ip.G2;
+    pp.G2half = ip.G2half;
+    pp.invG2 = ip.invG2;
+    pp.boundary = ip.boundary;
+    const int hw = (2 * ip.R + 1) * (pass == 0 ? ip.C : 1);
+    pp.win_pitch = pass_win_pitch(npl, hw);
+    pp.win_shift = (4 - hw % 4) % 4;
+    return pp;
+}
+
+// Both passes on `stream`, through an intermediate allocated in stream order.
+int launch_two_pass(const ImgParams& ip, hipStream_t stream)
+{
+    void* mid = nullptr;
+    const size_t bytes = size_t(ip.H) * size_t(ip.W) * size_t(ip.C) * 4;
+    if (hipMallocAsync(&mid, bytes, stream) != hipSuccess)
+        return set_error(RSG_ENOMEM, "cannot allocate the %zu-byte intermediate of the two-pass path", bytes);
+    int rc = launch_pass(ip, 0, pass_params(ip, 0, mid), stream);
+    if (rc == RSG_OK) rc = launch_pass(ip, 1, pass_params(ip, 1, mid), stream);
+    if (hipFreeAsync(mid, stream) != hipSuccess && rc == RSG_OK)
+        rc = set_error(RSG_EDEVICE, "cannot release the two-pass intermediate");
+    return rc;
+}
+
+}  // namespace
+
 int launch_single(const ImgParams& ip, hipStream_t stream)
 {
+    if (ip.path == kPathTwoPass) return launch_two_pass(ip, stream);
     switch (ip.dtype) {
     case RSG_U8: return launch_single_u8(ip, stream);
     case RSG_F32: return launch_single_f32(ip, stream);
@@ -102,6 +177,13 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         if (rc != RSG_OK) return rc;
         pos += kv.second.size();
         ++ci;
+    }
+    // images planned for the two-pass path run their two passes after the
+    // persistent launches, on the same stream
+    for (int i = 0; i < nimg; ++i) {
+        if (h_imgs[i].path != kPathTwoPass) continue;
+        int rc = launch_single(h_imgs[i], stream);
+        if (rc != RSG_OK) return rc;
     }
     return RSG_OK;
 }

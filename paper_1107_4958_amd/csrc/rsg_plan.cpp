@@ -40,6 +40,21 @@ struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs; };
 std::once_flag g_tune_once;
 std::vector<TuneEntry> g_tune;
 std::atomic<int> g_hs_override{0};
+std::atomic<int> g_path_override{0};
+
+// Two-pass geometry: the smallest chunk (64 NPL samples) that holds the
+// window head (2R + 1) C and fits the LDS; 0 if none does.
+int pass_npl_for(int C, int hw)
+{
+    const int n0 = (C == 3) ? 12 : 8;
+    for (int npl : {n0, 2 * n0})
+        if (hw <= kWave * npl && pass_lds_bytes(npl, hw) <= kLdsLimit) return npl;
+    return 0;
+}
+
+// Wide boxes favour the two-pass path: the fused kernel's column ring needs
+// (2R + 2) x 256 bytes of LDS per wave and each segment re-reads 2R + 1 rows.
+constexpr int kTwoPassMinRC = 40;
 
 void load_tune_table()
 {
@@ -91,6 +106,7 @@ int default_hs(int H, int nstrips, int R, uint32_t lds)
 }  // namespace
 
 void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_order_relaxed); }
+void set_path_override(int path) { g_path_override.store(path, std::memory_order_relaxed); }
 
 int plan_image(const rsg_image_desc& d, ImgParams* ip)
 {
@@ -155,9 +171,25 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         p.dc32 = float(dc);
     }
 
+    // ---- path: fused kernel, or two passes for wide boxes ----
+    const int C = d.C;
+    p.pnpl[0] = pass_npl_for(C, (2 * R + 1) * C);
+    p.pnpl[1] = pass_npl_for(1, 2 * R + 1);
+    const bool two_ok = p.pnpl[0] > 0 && p.pnpl[1] > 0;
+    if (two_ok) {
+        p.plds[0] = pass_lds_bytes(p.pnpl[0], (2 * R + 1) * C);
+        p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1);
+    }
+    const int ov = g_path_override.load(std::memory_order_relaxed);
+    bool two = two_ok && R * C >= kTwoPassMinRC;
+    if (ov == 1) two = false;
+    if (ov == 2) {
+        if (!two_ok) return set_error(RSG_EUNSUPPORTED, "two-pass path: box half-width %d too wide for C=%d", R, C);
+        two = true;
+    }
+
     // ---- row-scan layout: first (lanes per row, samples per lane) whose
     //      segment covers the row span [s0 - (R+1)C, s0 + 64 + RC) ----
-    const int C = d.C;
     int seg = 0, npl = 0, align = 1;
     for (int i = 0; i < kLayouts && !seg; ++i) {
         int sg, n;
@@ -168,11 +200,25 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         const int64_t span = int64_t(kWave) + int64_t(2 * R + 1) * C + al - 1;
         if (span <= int64_t(sg) * n) { seg = sg; npl = n; align = al; }
     }
-    if (!seg) {
-        int sg, n;
-        scan_layout(C, kLayouts - 1, &sg, &n);
-        return set_error(RSG_EUNSUPPORTED, "box half-width %d too wide for C=%d (largest row span %d samples)",
-                         R, C, sg * n);
+    if (!seg && !two) {
+        if (two_ok && ov != 1) {
+            two = true;
+        } else {
+            int sg, n;
+            scan_layout(C, kLayouts - 1, &sg, &n);
+            return set_error(RSG_EUNSUPPORTED, "box half-width %d too wide for C=%d (largest row span %d samples)",
+                             R, C, sg * n);
+        }
+    }
+    if (two) {
+        p.path = kPathTwoPass;
+        p.nstrips = int((WC + kWave - 1) / kWave);
+        p.hs = d.H;
+        p.nsegs = 1;
+        p.ntasks = (d.H + kPassRowsHost - 1) / kPassRowsHost + int((WC + kPassRowsHost - 1) / kPassRowsHost);
+        p.lds_bytes = std::max(p.plds[0], p.plds[1]);
+        *ip = p;
+        return RSG_OK;
     }
     p.seg = seg;
     p.npl = npl;

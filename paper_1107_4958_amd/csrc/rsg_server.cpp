@@ -237,6 +237,8 @@ int rsg_submit(rsg_server* s, const rsg_image_desc* req, uint64_t* ticket)
     if (rc != RSG_OK) return rc;
     const int es = dtype_size(req->dt);
     r.footprint = size_t(int64_t(req->H) * r.plan.src_stride * es) + size_t(int64_t(req->H) * r.plan.dst_stride * es);
+    if (r.plan.path == kPathTwoPass)        // its intermediate, allocated in stream order at launch
+        r.footprint += size_t(req->H) * size_t(req->W) * size_t(req->C) * 4;
     const size_t per_slot = s->slots.empty() ? 0 : s->slots[0].ws_bytes;
     if (s->cfg.hbm_budget && r.footprint > s->cfg.hbm_budget)
         return set_error(RSG_ENOMEM, "request needs %zu bytes, budget is %zu", r.footprint, s->cfg.hbm_budget);

@@ -161,3 +161,46 @@ def test_any_segment_height_gives_the_oracle(dtype, H, W, C, sigma, K):
             _check(img, dtype, sigma, K, oracle.REPLICATE)
     finally:
         rsg.rsg_tune_override(0)
+
+
+TWO_PASS_SHAPES = [
+    (1, 1, 1, 2.0, 3, 0), (5, 3, 1, 8.0, 5, 1), (1, 300, 1, 3.0, 3, 0), (300, 1, 1, 3.0, 4, 1),
+    (97, 250, 2, 4.0, 4, 0), (61, 211, 3, 6.0, 5, 1), (200, 333, 1, 8.0, 3, 0), (130, 77, 3, 20.0, 4, 0),
+    (257, 259, 1, 32.0, 5, 1), (700, 300, 1, 12.0, 5, 0), (1000, 129, 1, 40.0, 3, 0), (33, 2000, 4, 5.0, 3, 1),
+    (520, 1030, 1, 64.0, 5, 0), (64, 64, 1, 1.0, 1, 0),
+]
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("H,W,C,sigma,K,boundary", TWO_PASS_SHAPES)
+def test_two_pass_path(dtype, H, W, C, sigma, K, boundary):
+    """The two-pass path (row filter into a transposed intermediate, twice)
+    forced on every shape: uint8 bit-exact, floats within the same bars."""
+    import paper_1107_4958_amd as rsg
+    if dtype in ("f16", "bf16") and boundary:
+        pytest.skip("half formats are covered with the replicate boundary")
+    img = synthimg.image(H, W, C, dtype, 41)
+    rsg.rsg_tune_path(rsg.RSG_PATH_TWO_PASS)
+    try:
+        _check(img, dtype, sigma, K, boundary)
+    finally:
+        rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_paths_agree(dtype):
+    """Fused and two-pass results of one image: identical for uint8, within
+    the FP32 bar for floats."""
+    import paper_1107_4958_amd as rsg
+    img = synthimg.image(384, 700, 3, dtype, 43)
+    outs = []
+    for path in (rsg.RSG_PATH_FUSED, rsg.RSG_PATH_TWO_PASS):
+        rsg.rsg_tune_path(path)
+        try:
+            outs.append(gpu_filter(img, dtype, 16.0, 4, 0))
+        finally:
+            rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+    if dtype == "u8":
+        assert np.array_equal(outs[0], outs[1])
+    else:
+        assert rel_max_err(outs[1], outs[0].astype(np.float64)) <= FP32_TOL

@@ -24,8 +24,14 @@ def test_plan_shape_basics():
     hs, tasks, lds = rsg.rsg_plan_shape(_desc(4096, 4096))
     assert 1 <= hs <= 4096 and lds > 0
     assert tasks == 64 * -(-4096 // hs)             # 64-sample strips x segments
-    hs3, tasks3, _ = rsg.rsg_plan_shape(_desc(100, 70, C=3, dt=rsg.RSG_U8))
-    assert tasks3 == -(-210 // 64) * -(-100 // hs3)
+    try:
+        rsg.rsg_tune_path(rsg.RSG_PATH_FUSED)
+        hs3, tasks3, _ = rsg.rsg_plan_shape(_desc(100, 70, C=3, dt=rsg.RSG_U8))
+        assert tasks3 == -(-210 // 64) * -(-100 // hs3)
+    finally:
+        rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+    hs3, tasks3, _ = rsg.rsg_plan_shape(_desc(100, 70, C=3, dt=rsg.RSG_U8))    # R * C = 57: two passes
+    assert hs3 == 100 and tasks3 == -(-100 // 16) + -(-210 // 16)
 
 
 def test_override_and_clamp():
@@ -44,9 +50,15 @@ def test_huge_stride_shrinks_segments_or_is_refused():
     makes the planner shorten segments, an absurd one is refused."""
     hs, _, _ = rsg.rsg_plan_shape(_desc(4096, 64, stride=1 << 20))
     assert hs * (1 << 22) < (1 << 30)
-    with pytest.raises(rsg.RsgError) as e:
-        rsg.rsg_plan_shape(_desc(64, 64, sigma=30.0, stride=1 << 26))
-    assert e.value.code == rsg.RSG_EUNSUPPORTED
+    try:
+        rsg.rsg_tune_path(rsg.RSG_PATH_FUSED)
+        with pytest.raises(rsg.RsgError) as e:
+            rsg.rsg_plan_shape(_desc(64, 64, sigma=30.0, stride=1 << 26))
+        assert e.value.code == rsg.RSG_EUNSUPPORTED
+    finally:
+        rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+    # the two-pass path addresses each row on its own: any stride is fine
+    assert rsg.rsg_plan_shape(_desc(64, 64, sigma=30.0, stride=1 << 26))[0] == 64
 
 
 def _plans_with_table(path):
@@ -76,3 +88,19 @@ def test_tuning_table_lookup(tmp_path):
     assert b == b0                 # work size outside the line: built-in rule
     assert c == 40                 # uint8 line
     assert d == d0                 # R outside the line's range: built-in rule
+
+
+def test_wide_boxes_take_the_two_pass_path():
+    hs, tasks, lds = rsg.rsg_plan_shape(_desc(8192, 8192, sigma=64.0, K=5))
+    assert hs == 8192 and tasks == 8192 // 16 + 8192 // 16
+    hs8, _, _ = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))
+    assert hs8 < 4096                              # narrow boxes stay fused
+    try:
+        rsg.rsg_tune_path(rsg.RSG_PATH_FUSED)
+        assert rsg.rsg_plan_shape(_desc(8192, 8192, sigma=64.0, K=5))[0] < 8192
+        rsg.rsg_tune_path(rsg.RSG_PATH_TWO_PASS)
+        assert rsg.rsg_plan_shape(_desc(64, 64, sigma=1.0, K=3))[0] == 64
+        with pytest.raises(rsg.RsgError):
+            rsg.rsg_tune_path(3)
+    finally:
+        rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
