@@ -8,10 +8,13 @@ segment of hs output rows, streaming 2R + 1 extra rows above the segment
 (R: largest box half-width).  Short segments give many tasks but re-read
 the halo often; long ones give few tasks.  The best hs depends on the
 element type, the channel count, R and the amount of work (strips x rows),
-so the table is keyed on exactly those: lines "dtype C rlo rhi nlo nhi hs".
+so the table is keyed on exactly those: lines "dtype C rlo rhi nlo nhi hs",
+with hs = -1 selecting the two-pass path (row filter into a transposed
+intermediate, twice), which wins for wide boxes.
 
 For every (dtype, C, image side, sigma, K) point the script times each
-candidate height through rsg_tune_override on rotating synthetic images
+candidate height through rsg_tune_override, and the two-pass path through
+rsg_tune_path, on rotating synthetic images
 resident in HBM (timed with HIP events on the launch stream) and keeps the
 fastest.  Points are then turned into buckets: R ranges split halfway
 between measured R values, work ranges split at the geometric middle
@@ -32,6 +35,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "tune_gfx950.txt")
 
 CANDIDATES = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048)
+TWO_PASS = -1                      # table value for the two-pass path
+DEFAULT = -2                       # key of the built-in rule's timing
 POINTS = ((1.0, 3), (2.0, 3), (4.0, 5), (8.0, 3), (16.0, 4), (32.0, 5), (64.0, 5))
 SIDES = (512, 1024, 2048, 4096, 8192)
 MAX_SAMPLES = 8192 * 8192          # per image (side^2 * C)
@@ -57,14 +62,18 @@ def _time_config(rsg, torch, dt, side, C, sigma, K, reps):
     stream = torch.cuda.current_stream()
     code = rsg.tensor_dtype_code(base)
     out = {}
-    for hs in (0,) + tuple(h for h in CANDIDATES if h <= side):
-        rsg.rsg_tune_override(hs)
+    # 0: the built-in rule; h > 0: the fused kernel with segment height h;
+    # TWO_PASS: the two-pass path
+    for hs in (0,) + tuple(h for h in CANDIDATES if h <= side) + (TWO_PASS,):
+        rsg.rsg_tune_path(rsg.RSG_PATH_TWO_PASS if hs == TWO_PASS else
+                          (rsg.RSG_PATH_FUSED if hs > 0 else rsg.RSG_PATH_AUTO))
+        rsg.rsg_tune_override(max(hs, 0))
         try:
             d = rsg.make_desc(srcs[0], dsts[0], sigma, K)
             plan_hs = rsg.rsg_plan_shape(d)[0]
         except rsg.RsgError:
             continue
-        if hs and plan_hs != hs:
+        if hs > 0 and plan_hs != hs:
             continue                                  # clamped to another candidate
 
         def launch(i):
@@ -80,8 +89,9 @@ def _time_config(rsg, torch, dt, side, C, sigma, K, reps):
             launch(i)
         e1.record(stream)
         torch.cuda.synchronize()
-        out[hs if hs else -plan_hs] = e0.elapsed_time(e1) / reps * 1000.0
+        out[hs if hs else DEFAULT] = e0.elapsed_time(e1) / reps * 1000.0
     rsg.rsg_tune_override(0)
+    rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
     del srcs, dsts, base
     return out
 
@@ -128,15 +138,17 @@ def main(argv=None):
                     res = _time_config(rsg, torch, dt, side, C, sigma, K, reps)
                     if not res:
                         continue
-                    default = [v for k, v in res.items() if k < 0]
-                    tuned = {k: v for k, v in res.items() if k > 0}
+                    default = [v for k, v in res.items() if k == DEFAULT]
+                    tuned = {k: v for k, v in res.items() if k != DEFAULT}
                     best = min(tuned, key=tuned.get)
                     n = -(-side * C // 64) * side
                     rows.append(dict(dt=dt, C=C, R=R, n=n, hs=best, us=tuned[best],
                                      default_us=default[0] if default else float("nan"),
                                      side=side, sigma=sigma, K=K))
-                    print("%-4s C=%d side=%5d sigma=%5.1f K=%d R=%3d: best hs=%4d %8.1f us (built-in rule %8.1f us)"
-                          % (dt, C, side, sigma, K, R, best, tuned[best], rows[-1]["default_us"]), flush=True)
+                    print("%-4s C=%d side=%5d sigma=%5.1f K=%d R=%3d: best %s %8.1f us (built-in rule %8.1f us%s)"
+                          % (dt, C, side, sigma, K, R, "two-pass" if best == TWO_PASS else "hs=%4d" % best,
+                             tuned[best], rows[-1]["default_us"],
+                             ", two-pass %.1f us" % tuned[TWO_PASS] if TWO_PASS in tuned else ""), flush=True)
 
     code = {"u8": 0, "f32": 1, "f16": 2, "bf16": 3}
     lines = ["# segment heights measured by paper_1107_4958_amd/autotune.py on %s (%.0f s)"

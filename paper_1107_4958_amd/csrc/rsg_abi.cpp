@@ -37,7 +37,7 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
             std::string msg = g_last_error;
             return set_error(rc, "image %d: %s", i, msg.c_str());
         }
-        if (imgs[i].path == kPathFused) total += imgs[i].ntasks;
+        total += imgs[i].ntasks;                  // fused tasks or two-pass row blocks
     }
     if (total > (int64_t(1) << 30)) return set_error(RSG_EUNSUPPORTED, "batch too large");
     tasks.reserve(size_t(total));
@@ -121,7 +121,7 @@ int rsg_filter_batch_workspace(const rsg_image_desc* d, int n, size_t* bytes)
     std::vector<rsg::BatchTask> tasks;
     int rc = rsg::plan_batch(d, n, imgs, tasks);
     if (rc != RSG_OK) return rc;
-    *bytes = rsg::batch_workspace_bytes(n, int(tasks.size()));
+    *bytes = rsg::batch_workspace_bytes(n, int(int64_t(tasks.size()) + rsg::pass_blocks(imgs.data(), n)));
     return RSG_OK;
 }
 

@@ -59,6 +59,7 @@ struct ImgParams {
     // two-pass path (wide boxes): row filter + transposed store, twice
     int32_t path;                  // kPathFused or kPathTwoPass
     int32_t pnpl[2];               // samples per lane of pass A, pass B
+    int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
     uint32_t plds[2];              // LDS bytes per workgroup of pass A, pass B
 };
 
@@ -112,12 +113,30 @@ int launch_pass_u8(const ImgParams& ip, int pass, const PassParams& pp, hipStrea
 int launch_pass_f32(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
 int launch_pass_f16(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
 int launch_pass_bf16(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t stream);
+// One launch of one pass over the two-pass images of a batch that share a
+// kernel instantiation: workgroup b takes (pass parameters, row block) =
+// d_tasks[b].
+struct PassBatchLaunch {
+    int dtype, pass, C, npl, kt, stages;
+    uint32_t lds;
+    const PassParams* d_pps;
+    const int2* d_tasks;
+    int ntasks;
+};
+int launch_pass_batch(const PassBatchLaunch& b, hipStream_t stream);
+int launch_pass_batch_u8(const PassBatchLaunch& b, hipStream_t stream);
+int launch_pass_batch_f32(const PassBatchLaunch& b, hipStream_t stream);
+int launch_pass_batch_f16(const PassBatchLaunch& b, hipStream_t stream);
+int launch_pass_batch_bf16(const PassBatchLaunch& b, hipStream_t stream);
+// Row blocks of the two-pass images of a batch (both passes).
+int64_t pass_blocks(const ImgParams* imgs, int nimg);
 // Window geometry of one pass (shared by the planner and the launcher).
 constexpr int kPassRowsHost = 16;
 inline int pass_win_pitch(int npl, int hw) { return (kWave * npl + hw + 3 + 3) / 4 * 4; }
-inline uint32_t pass_lds_bytes(int npl, int hw)
+// stages: staging tiles (2 lets the stores of chunk k overlap chunk k + 1)
+inline uint32_t pass_lds_bytes(int npl, int hw, int stages)
 {
-    return uint32_t(4 * (kPassRowsHost * pass_win_pitch(npl, hw) + kWave * npl * (kPassRowsHost + 1)));
+    return uint32_t(4 * (kPassRowsHost * pass_win_pitch(npl, hw) + stages * kWave * npl * (kPassRowsHost + 1)));
 }
 // One persistent launch over the tasks of one (dtype, C, kt) class.
 struct BatchClassLaunch {
@@ -162,6 +181,7 @@ inline uint32_t tile_lds_bytes(int seg, int npl, int L)
 // NULL stages through pageable memory.
 int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, int ntasks,
                  void* d_ws, size_t ws_bytes, hipStream_t stream, void* h_stage = nullptr);
+// ntasks: tasks of the fused images plus row blocks of the two-pass images.
 size_t batch_workspace_bytes(int nimg, int ntasks);
 
 // Sizes of the element types.

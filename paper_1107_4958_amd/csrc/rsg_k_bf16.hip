@@ -18,4 +18,9 @@ int launch_pass_bf16(const ImgParams& ip, int pass, const PassParams& pp, hipStr
     return dispatch::launch_pass_t<dev::TrBF16>(ip, pass, pp, stream);
 }
 
+int launch_pass_batch_bf16(const PassBatchLaunch& b, hipStream_t stream)
+{
+    return dispatch::launch_pass_batch_t<dev::TrBF16>(b, stream);
+}
+
 }  // namespace rsg

@@ -18,4 +18,9 @@ int launch_pass_f16(const ImgParams& ip, int pass, const PassParams& pp, hipStre
     return dispatch::launch_pass_t<dev::TrF16>(ip, pass, pp, stream);
 }
 
+int launch_pass_batch_f16(const PassBatchLaunch& b, hipStream_t stream)
+{
+    return dispatch::launch_pass_batch_t<dev::TrF16>(b, stream);
+}
+
 }  // namespace rsg

@@ -18,4 +18,9 @@ int launch_pass_u8(const ImgParams& ip, int pass, const PassParams& pp, hipStrea
     return dispatch::launch_pass_t<dev::TrU8>(ip, pass, pp, stream);
 }
 
+int launch_pass_batch_u8(const PassBatchLaunch& b, hipStream_t stream)
+{
+    return dispatch::launch_pass_batch_t<dev::TrU8>(b, stream);
+}
+
 }  // namespace rsg

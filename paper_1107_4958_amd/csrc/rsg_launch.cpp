@@ -114,24 +114,73 @@ size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 constexpr int kMaxClasses = 4 * 4 * 3;   // dtype x C x taps
 }  // namespace
 
-// Workspace: [counters, one per class][ImgParams x nimg][BatchTask x ntasks]
+int64_t pass_blocks(const ImgParams* imgs, int nimg)
+{
+    int64_t n = 0;
+    for (int i = 0; i < nimg; ++i)
+        if (imgs[i].path == kPathTwoPass) n += imgs[i].ntasks;
+    return n;
+}
+
+// Workspace: [counters, one per class][ImgParams x nimg][task entries x ntasks]
+// [PassParams x 2 nimg].  Task entries (8 bytes) are the fused images'
+// BatchTasks followed by the (pass parameters, row block) pairs of the
+// two-pass images.
 size_t batch_workspace_bytes(int nimg, int ntasks)
 {
     return up(sizeof(unsigned) * kMaxClasses) + up(sizeof(ImgParams) * size_t(nimg)) +
-           up(sizeof(BatchTask) * size_t(ntasks));
+           up(sizeof(BatchTask) * size_t(ntasks)) + up(sizeof(PassParams) * 2 * size_t(nimg));
 }
 
 int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, int ntasks, void* d_ws,
                  size_t ws_bytes, hipStream_t stream, void* h_stage)
 {
-    const size_t need = batch_workspace_bytes(nimg, ntasks);
+    static_assert(sizeof(BatchTask) == sizeof(int2), "task entries share one region");
+    const int64_t nblocks = pass_blocks(h_imgs, nimg);
+    const size_t need = batch_workspace_bytes(nimg, int(ntasks + nblocks));
     if (ws_bytes < need) return set_error(RSG_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, need);
-    // group the tasks by kernel class, keeping their order inside a class
+
+    // fused images: group the tasks by kernel class, keeping their order
     std::map<std::tuple<int, int, int>, std::vector<BatchTask>> classes;
     for (int t = 0; t < ntasks; ++t) {
         const ImgParams& ip = h_imgs[h_tasks[t].img];
         classes[std::make_tuple(ip.dtype, ip.C, ip.kt)].push_back(h_tasks[t]);
     }
+
+    // two-pass images: one intermediate for all, pass parameters 2j (A) and
+    // 2j + 1 (B) for the j-th of them, row blocks grouped by instantiation
+    std::vector<int> two;
+    size_t mid_bytes = 0;
+    for (int i = 0; i < nimg; ++i)
+        if (h_imgs[i].path == kPathTwoPass) {
+            two.push_back(i);
+            mid_bytes += up(size_t(h_imgs[i].H) * size_t(h_imgs[i].W) * size_t(h_imgs[i].C) * 4);
+        }
+    void* mid = nullptr;
+    if (!two.empty() && hipMallocAsync(&mid, mid_bytes, stream) != hipSuccess)
+        return set_error(RSG_ENOMEM, "cannot allocate the %zu-byte intermediate of the two-pass images", mid_bytes);
+    std::vector<PassParams> pps(2 * two.size());
+    using PassKey = std::tuple<int, int, int, int, int, int>;     // pass, dtype, C, npl, kt, stages
+    std::map<PassKey, std::vector<int2>> pclasses;
+    std::map<PassKey, uint32_t> plds;
+    {
+        size_t off = 0;
+        for (size_t j = 0; j < two.size(); ++j) {
+            const ImgParams& ip = h_imgs[two[j]];
+            void* slice = static_cast<char*>(mid) + off;
+            off += up(size_t(ip.H) * size_t(ip.W) * size_t(ip.C) * 4);
+            for (int pass = 0; pass < 2; ++pass) {
+                pps[2 * j + pass] = pass_params(ip, pass, slice);
+                const PassKey key(pass, ip.dtype, pass == 0 ? ip.C : 1, ip.pnpl[pass], ip.kt, ip.pst[pass]);
+                const int rows = pps[2 * j + pass].rows;
+                auto& v = pclasses[key];
+                for (int blk = 0; blk < (rows + kPassRowsHost - 1) / kPassRowsHost; ++blk)
+                    v.push_back(int2{int(2 * j + pass), blk});
+                plds[key] = std::max(plds[key], ip.plds[pass]);
+            }
+        }
+    }
+
     std::vector<char> pageable;
     char* host = static_cast<char*>(h_stage);
     if (!host) {
@@ -142,12 +191,18 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
     }
     const size_t o_img = up(sizeof(unsigned) * kMaxClasses);
     const size_t o_task = o_img + up(sizeof(ImgParams) * size_t(nimg));
+    const size_t o_pp = o_task + up(sizeof(BatchTask) * size_t(ntasks + nblocks));
     std::memcpy(host + o_img, h_imgs, sizeof(ImgParams) * size_t(nimg));
     size_t pos = 0;
     for (auto& kv : classes) {
         std::memcpy(host + o_task + pos * sizeof(BatchTask), kv.second.data(), sizeof(BatchTask) * kv.second.size());
         pos += kv.second.size();
     }
+    for (auto& kv : pclasses) {
+        std::memcpy(host + o_task + pos * sizeof(int2), kv.second.data(), sizeof(int2) * kv.second.size());
+        pos += kv.second.size();
+    }
+    if (!pps.empty()) std::memcpy(host + o_pp, pps.data(), sizeof(PassParams) * pps.size());
     hipError_t e = hipMemcpyAsync(d_ws, host, need, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return set_error(RSG_EDEVICE, "workspace copy failed: %s", hipGetErrorString(e));
 
@@ -178,14 +233,39 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         pos += kv.second.size();
         ++ci;
     }
-    // images planned for the two-pass path run their two passes after the
-    // persistent launches, on the same stream
-    for (int i = 0; i < nimg; ++i) {
-        if (h_imgs[i].path != kPathTwoPass) continue;
-        int rc = launch_single(h_imgs[i], stream);
-        if (rc != RSG_OK) return rc;
+    // two-pass images: every pass-A class, then every pass-B class (the map
+    // orders the keys by pass first), so each image's pass B follows its A
+    int rc = RSG_OK;
+    for (auto& kv : pclasses) {
+        PassBatchLaunch b;
+        b.pass = std::get<0>(kv.first);
+        b.dtype = std::get<1>(kv.first);
+        b.C = std::get<2>(kv.first);
+        b.npl = std::get<3>(kv.first);
+        b.kt = std::get<4>(kv.first);
+        b.stages = std::get<5>(kv.first);
+        b.lds = plds[kv.first];
+        b.d_pps = reinterpret_cast<const PassParams*>(ws + o_pp);
+        b.d_tasks = reinterpret_cast<const int2*>(ws + o_task) + pos;
+        b.ntasks = int(kv.second.size());
+        rc = launch_pass_batch(b, stream);
+        if (rc != RSG_OK) break;
+        pos += kv.second.size();
     }
-    return RSG_OK;
+    if (mid && hipFreeAsync(mid, stream) != hipSuccess && rc == RSG_OK)
+        rc = set_error(RSG_EDEVICE, "cannot release the two-pass intermediate");
+    return rc;
+}
+
+int launch_pass_batch(const PassBatchLaunch& b, hipStream_t stream)
+{
+    switch (b.dtype) {
+    case RSG_U8: return launch_pass_batch_u8(b, stream);
+    case RSG_F32: return launch_pass_batch_f32(b, stream);
+    case RSG_F16: return launch_pass_batch_f16(b, stream);
+    case RSG_BF16: return launch_pass_batch_bf16(b, stream);
+    default: return set_error(RSG_EINVAL, "bad dtype %d", b.dtype);
+    }
 }
 
 }  // namespace rsg

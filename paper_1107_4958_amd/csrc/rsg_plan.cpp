@@ -34,8 +34,8 @@ int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
 // Tuning table (text): lines "dtype C rlo rhi nlo nhi hs", '#' starts a
 // comment.  An image of dtype and channel count C whose largest half-width R
 // lies in [rlo, rhi] and whose work size n = strips * H (strips of 64
-// samples) lies in [nlo, nhi] takes segment height hs from the first
-// matching line.
+// samples) lies in [nlo, nhi] takes the fused kernel with segment height hs
+// from the first matching line, or the two-pass path if hs is -1.
 struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs; };
 std::once_flag g_tune_once;
 std::vector<TuneEntry> g_tune;
@@ -43,12 +43,16 @@ std::atomic<int> g_hs_override{0};
 std::atomic<int> g_path_override{0};
 
 // Two-pass geometry: the smallest chunk (64 NPL samples) that holds the
-// window head (2R + 1) C and fits the LDS; 0 if none does.
-int pass_npl_for(int C, int hw)
+// window head (2R + 1) C and fits the LDS with one staging tile (0 if none
+// does), and two staging tiles when those fit too.
+int pass_npl_for(int C, int hw, int* stages)
 {
     const int n0 = (C == 3) ? 12 : 8;
     for (int npl : {n0, 2 * n0})
-        if (hw <= kWave * npl && pass_lds_bytes(npl, hw) <= kLdsLimit) return npl;
+        if (hw <= kWave * npl && pass_lds_bytes(npl, hw, 1) <= kLdsLimit) {
+            *stages = pass_lds_bytes(npl, hw, 2) <= kLdsLimit ? 2 : 1;
+            return npl;
+        }
     return 0;
 }
 
@@ -67,7 +71,8 @@ void load_tune_table()
         if (h != std::string::npos) line.resize(h);
         std::istringstream is(line);
         TuneEntry e;
-        if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.nlo >> e.nhi >> e.hs && e.hs > 0) g_tune.push_back(e);
+        if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.nlo >> e.nhi >> e.hs && (e.hs > 0 || e.hs == -1))
+            g_tune.push_back(e);
     }
 }
 
@@ -173,15 +178,17 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
 
     // ---- path: fused kernel, or two passes for wide boxes ----
     const int C = d.C;
-    p.pnpl[0] = pass_npl_for(C, (2 * R + 1) * C);
-    p.pnpl[1] = pass_npl_for(1, 2 * R + 1);
+    p.pnpl[0] = pass_npl_for(C, (2 * R + 1) * C, &p.pst[0]);
+    p.pnpl[1] = pass_npl_for(1, 2 * R + 1, &p.pst[1]);
     const bool two_ok = p.pnpl[0] > 0 && p.pnpl[1] > 0;
     if (two_ok) {
-        p.plds[0] = pass_lds_bytes(p.pnpl[0], (2 * R + 1) * C);
-        p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1);
+        p.plds[0] = pass_lds_bytes(p.pnpl[0], (2 * R + 1) * C, p.pst[0]);
+        p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1, p.pst[1]);
     }
     const int ov = g_path_override.load(std::memory_order_relaxed);
-    bool two = two_ok && R * C >= kTwoPassMinRC;
+    int hs_t = 0;
+    const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t);
+    bool two = two_ok && (tabled ? hs_t < 0 : R * C >= kTwoPassMinRC);
     if (ov == 1) two = false;
     if (ov == 2) {
         if (!two_ok) return set_error(RSG_EUNSUPPORTED, "two-pass path: box half-width %d too wide for C=%d", R, C);
@@ -210,7 +217,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
                              R, C, sg * n);
         }
     }
-    if (two) {
+    auto finish_two_pass = [&]() {
         p.path = kPathTwoPass;
         p.nstrips = int((WC + kWave - 1) / kWave);
         p.hs = d.H;
@@ -219,7 +226,8 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         p.lds_bytes = std::max(p.plds[0], p.plds[1]);
         *ip = p;
         return RSG_OK;
-    }
+    };
+    if (two) return finish_two_pass();
     p.seg = seg;
     p.npl = npl;
     p.align = align;
@@ -236,8 +244,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     p.nstrips = int((WC + kWave - 1) / kWave);
 
     // ---- segment height ----
-    int hs = 0;
-    if (!tuned_hs(d.dt, C, R, int64_t(p.nstrips) * d.H, &hs)) hs = default_hs(d.H, p.nstrips, R, p.lds_bytes);
+    int hs = (tabled && hs_t > 0) ? hs_t : default_hs(d.H, p.nstrips, R, p.lds_bytes);
     hs = std::max(1, std::min(hs, d.H));
     {   // every offset a task touches (rows ybase .. ybase + its padded
         // iteration count, times the larger stride) must stay below 2^30
@@ -247,9 +254,11 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
             return rows * stride_b + WC * es <= kOffsetLimit;
         };
         while (hs > 1 && !fits(hs)) hs = (hs + 1) / 2;
-        if (!fits(hs))
+        if (!fits(hs)) {
+            if (two_ok && ov != 1) return finish_two_pass();     // it addresses every row on its own
             return set_error(RSG_EUNSUPPORTED, "row stride too large for a tile (%lld bytes, box half-width %d)",
                              (long long)stride_b, R);
+        }
     }
     p.hs = hs;
     p.nsegs = (d.H + hs - 1) / hs;

@@ -21,7 +21,9 @@
 // running sums of positions [k CW - (2R + 1) C, (k + 1) CW); after the chunk
 // its last (2R + 1) C entries move to the front.  Outputs go to an LDS
 // staging tile [CW][kPassRows + 1], then the workgroup stores them
-// transposed: kPassRows consecutive elements per output row.
+// transposed: kPassRows consecutive elements per output row.  With two
+// staging tiles (ST = 2, when the LDS allows) chunk k + 1 fills the other
+// tile while chunk k's stores drain, and one barrier per chunk suffices.
 //
 // Precision: integer inputs use exact uint32 running sums (differences are
 // exact modulo 2^32).  Float inputs subtract a per-row reference (the row's
@@ -71,7 +73,7 @@ __device__ __forceinline__ int pass_clamp(int pos, int len, bool replicate)
     return pos < 0 ? c : len - C + c;
 }
 
-template <class TrIn, int OUT, int C, int NPL, int KT>
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
 __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32_t* lds)
 {
     using Acc = typename TrIn::Acc;
@@ -90,7 +92,7 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
 
     // per-wave window (the head starts so that the new part is 16-byte aligned)
     Acc* win = reinterpret_cast<Acc*>(lds) + wave * p.win_pitch + p.win_shift;
-    uint32_t* stg = lds + TR * p.win_pitch;
+    uint32_t* stg0 = lds + TR * p.win_pitch;
 
     const int row0 = block * TR;
     const int row = min(row0 + wave, p.rows - 1);  // a wave past the last row repeats it and stores nothing
@@ -193,16 +195,23 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
     }
 
     const int nchunks = (len + R * C + CW - 1) / CW;
-    Acc vnext[NPL];
-    load_samples(0, vnext);
+    constexpr int PFC = 1;                         // chunks of loads in flight ahead of the one in use
+    Acc vq[PFC][NPL];
+#pragma unroll
+    for (int b = 0; b < PFC; ++b) load_samples(b * CW, vq[b]);
     for (int k = 0; k < nchunks; ++k) {
         Acc v[NPL];
 #pragma unroll
-        for (int i = 0; i < NPL; ++i) v[i] = vnext[i];
-        if (k + 1 < nchunks) load_samples((k + 1) * CW, vnext);      // next chunk in flight
+        for (int i = 0; i < NPL; ++i) v[i] = vq[0][i];
+#pragma unroll
+        for (int b = 0; b + 1 < PFC; ++b)
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) vq[b][i] = vq[b + 1][i];
+        if (k + PFC < nchunks) load_samples((k + PFC) * CW, vq[PFC - 1]);   // chunks in flight
         scan_store(v, carry, HW, true);
         wave_lds_fence();
 
+        uint32_t* stg = stg0 + (ST > 1 ? (k & 1) * CW * SP : 0);
         // outputs o = lane + 64 t of this chunk (position k CW - R C + o)
 #pragma unroll
         for (int t = 0; t < NPL; ++t) {
@@ -261,15 +270,27 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
             if (x >= 0 && x < len && row0 + w < p.rows)
                 store_pass_out<OUT>(p.dst, int64_t(x) * p.dst_stride + row0 + w, stg[o * SP + w]);
         }
-        __syncthreads();
+        // with two staging tiles the next chunk writes the other one; the
+        // barrier of that chunk orders this chunk's reads before its reuse
+        if (ST == 1) __syncthreads();
     }
 }
 
-template <class TrIn, int OUT, int C, int NPL, int KT>
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
 __global__ __launch_bounds__(kPassRows * kWave) void k_pass(PassParams p)
 {
     extern __shared__ uint32_t lds[];
-    pass_rows<TrIn, OUT, C, NPL, KT>(p, blockIdx.x, lds);
+    pass_rows<TrIn, OUT, C, NPL, KT, ST>(p, blockIdx.x, lds);
+}
+
+// The same pass over the row blocks of several images (one per workgroup).
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
+__global__ __launch_bounds__(kPassRows * kWave) void k_pass_batch(const PassParams* __restrict__ pps,
+                                                                   const int2* __restrict__ tasks)
+{
+    extern __shared__ uint32_t lds[];
+    const int2 t = tasks[blockIdx.x];
+    pass_rows<TrIn, OUT, C, NPL, KT, ST>(pps[t.x], t.y, lds);
 }
 
 }  // namespace dev

@@ -201,7 +201,7 @@ def test_serve_budget_and_queue_limits():
     outs = [torch.empty_like(big) for _ in range(12)]
     arena = torch.empty(8 << 20, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    one = 2 * big.numel() * 4
+    one = 3 * big.numel() * 4       # src + dst (+ the intermediate if it is planned on the two-pass path)
     srv = _server(arena, hbm_budget=one, queue_depth=2, max_inflight=1, n_streams=1, max_batch=1)
     try:
         huge = torch.empty(8192, 8193, device="cuda")
@@ -241,3 +241,34 @@ def test_serve_destroy_drains():
     ref = _alone(src, 5.0, 4)
     for o in outs:
         assert torch.equal(o, ref)
+
+
+def test_batch_two_pass_identical_to_alone():
+    """Every image forced onto the two-pass path: the batch runs one launch
+    per pass and kernel class, and each image matches its single launch and
+    the oracle."""
+    import torch
+    rsg = _rsg()
+    rsg.rsg_tune_path(rsg.RSG_PATH_TWO_PASS)
+    try:
+        items = []
+        for it in _mixed_images():                # the images whose window fits the two-pass LDS budget
+            s = to_device(it["img"], it["dtype"])
+            try:
+                rsg.rsg_plan_shape(rsg.make_desc(s, torch.empty_like(s), it["sigma"], it["K"]))
+                items.append(it)
+            except rsg.RsgError:
+                pass
+        assert len(items) >= 8
+        srcs = [to_device(it["img"], it["dtype"]) for it in items]
+        dsts = [torch.full_like(s, 0) for s in srcs]
+        rsg.filter_batch_tensors(srcs, dsts, [it["sigma"] for it in items], [it["K"] for it in items])
+        torch.cuda.synchronize()
+        for it, s, d in zip(items, srcs, dsts):
+            alone = from_device(_alone(s, it["sigma"], it["K"]), it["dtype"])
+            got = from_device(d, it["dtype"])
+            assert np.array_equal(got.view(np.uint8), alone.view(np.uint8)), (it["H"], it["W"], it["C"], it["dtype"])
+            if it["dtype"] in ("u8", "f32"):
+                _spot_check(it["img"], got, it["dtype"], it["sigma"], it["K"])
+    finally:
+        rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
