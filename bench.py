@@ -12,11 +12,13 @@ fused kernel (algorithmic bytes per launch / average launch time from HIP
 events on the launch stream, against 8 TB/s HBM3E; HBM traffic from the
 committed rocprofv3 counter summary when it was taken on the current kernel
 sources), the CPU oracle baseline, the uint8 form of the headline and, unless
---quick: the sigma x K grid at 4096^2 (uint8 and FP32), the mixed batch (256
-three-channel uint8 images in one persistent launch against the same images
-filtered one launch each), the 8192^2 precision forms with their normalised
-RMS error against the FP64 oracle, and the served request stream's p50/p99
-latency and throughput.
+--quick: the sigma x K grid at 4096^2 (uint8 and FP32), the plain method at
+512^2 with its accuracy against the sampled Gaussian, the mixed batch (256
+three-channel uint8 images in one launch per kernel class against the same
+images filtered one launch each), the 8192^2 precision forms with their
+normalised RMS error against the FP64 box oracle and the sampled Gaussian,
+and the served request streams (p50/p99 latency and throughput at fractions
+of the measured saturation rate).
 """
 from __future__ import annotations
 
@@ -167,6 +169,26 @@ def sampled_parity(img, out, dtype, sigma, K, n=300):
 # ---------------------------------------------------------------------------
 # further workloads
 # ---------------------------------------------------------------------------
+def plain_workload(steps):
+    """The plain method on one 512 x 512 single-channel FP32 1/f image,
+    sigma = 5, K = 3: parity with the box oracle over the whole image, and
+    the method's accuracy against the sampled Gaussian (NRMS, PSNR)."""
+    import oracle
+    import synthimg
+    img = synthimg.image(512, 512, 1, "f32", 1)
+    ms, out = time_image(img, "f32", 5.0, 3, steps, 10, min_pool_bytes=64 << 20)
+    o = from_dev(out, "f32").astype(np.float64)
+    b = oracle.boxes(5.0, 3)
+    x = img.astype(np.float64)
+    ref = oracle.box_filter(x, b["r"], b["w32"].astype(np.float64))[..., 0]
+    g = oracle.gauss_filter(x, 5.0)[..., 0]
+    return {"H": 512, "W": 512, "sigma": 5.0, "K": 3, "r": [int(v) for v in b["r"]], "us": round(ms * 1000, 2),
+            "gpix_s": round(512 * 512 / (ms * 1e-3) / 1e9, 2),
+            "parity_max_rel_err": float("%.3g" % (np.max(np.abs(o - ref)) / np.max(np.abs(ref)))),
+            "nrms_vs_gauss": float("%.4g" % oracle.nrms(o, g)), "psnr_vs_gauss_db": round(oracle.psnr(o, g), 2),
+            "note": "2 MiB: resident in the last-level cache, no roofline"}
+
+
 def sigma_k_grid(imgs, steps):
     """Gpixel/s and HBM fraction at 4096^2 for sigma in {2, 8, 32}, K in {3, 4, 5}."""
     out = []
@@ -181,7 +203,7 @@ def sigma_k_grid(imgs, steps):
     return out
 
 
-def batch_workload(steps):
+def batch_workload(steps, headline_gsamples=None):
     """256 three-channel uint8 images (sides 64..2048, sigma log-uniform in
     [1, 30], K = 4) in one persistent launch, against the same images
     filtered with one launch each."""
@@ -213,17 +235,22 @@ def batch_workload(steps):
     ms_single = e0.elapsed_time(e1) / steps
     px = sum(s["H"] * s["W"] for s in specs)
     byt = 2 * sum(s["H"] * s["W"] * s["C"] for s in specs)
+    gs = byt / 2 / (ms_batch * 1e-3) / 1e9
     return {"images": len(specs), "pixels": px, "ms_per_batch": round(ms_batch, 4),
             "gpix_s": round(px / (ms_batch * 1e-3) / 1e9, 2),
+            "channel_gsamples_s": round(gs, 2),
+            "vs_single_image_fp32_gsamples": round(gs / headline_gsamples, 3) if headline_gsamples else None,
             "hbm_frac": round(byt / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "ms_one_launch_per_image": round(ms_single, 4),
             "speedup_vs_one_launch_per_image": round(ms_single / ms_batch, 2)}
 
 
-def precision_workload(steps, npts=8000):
+def precision_workload(steps, npts=8000, ngauss=2000):
     """8192^2 single-channel image in uint8 (exact integer sums), FP16 and
     BF16 storage (FP32 accumulation) and FP32; sigma in {4, 64}, K = 5.
-    NRMS error against the FP64 oracle of the same boxes on sampled points."""
+    NRMS error on sampled points against the FP64 oracle of the same boxes
+    (the arithmetic's error) and against the sampled Gaussian (the method's
+    error), both on each form's own input."""
     import oracle
     import synthimg
     H = W = 8192
@@ -240,10 +267,12 @@ def precision_workload(steps, npts=8000):
             o = from_dev(res, dtype)[ys, xs]
             im3 = decode(img, dtype)[..., None]
             ref = oracle.box_filter_points(im3, b["r"], b["w"], ys, xs)     # FP64 weights
+            gref = oracle.gauss_filter_points(im3, sigma, ys[:ngauss], xs[:ngauss])
             rec = {"dtype": dtype, "sigma": sigma, "K": 5, "ms": round(ms, 4),
                    "gpix_s": round(H * W / (ms * 1e-3) / 1e9, 2),
                    "hbm_frac": roofline(dtype, H, W, 1, ms)["frac"],
-                   "nrms_vs_fp64": float("%.3g" % oracle.nrms(decode(o, dtype), ref))}
+                   "nrms_vs_fp64_boxes": float("%.3g" % oracle.nrms(decode(o, dtype), ref)),
+                   "nrms_vs_gauss": float("%.3g" % oracle.nrms(decode(o, dtype)[:ngauss], gref))}
             if dtype == "u8":
                 exact = oracle.box_filter_u8_points(img[..., None], b["r"], b["m"], b["G"], ys, xs)
                 rec["bit_exact_vs_integer_oracle"] = bool(np.array_equal(o, exact))
@@ -251,74 +280,111 @@ def precision_workload(steps, npts=8000):
     return out
 
 
-def serving_workload(n=400, qps=1500.0):
-    """Poisson request stream (sides uniform in [128, 4096], C in {1, 3},
-    uint8 or FP32, sigma log-uniform in [0.5, 50], K in {3, 5}) served with
-    continuous batching under an HBM budget.  Sources are windows of
-    device-resident 4096^2 images (row stride = the resident image's);
-    outputs are preallocated.  Latency = done - submit per request."""
-    import torch
-    import paper_1107_4958_amd as rsg
-    import synthimg
-    reqs = synthimg.request_stream(n, qps)
-    fields = [synthimg.one_over_f(4096, 4096, 48 + c) for c in range(3)]
-    resident = {}
-    for dt in ("u8", "f32"):
-        for C in (1, 3):
-            resident[(dt, C)] = to_dev(np.stack([synthimg.to_dtype(f, dt) for f in fields[:C]], axis=-1), dt)
-    del fields
-    dsts = []
-    descs = []
-    for r in reqs:
-        src = resident[(r["dtype"], r["C"])]
-        dst = torch.empty((r["H"], r["W"], r["C"]), dtype=src.dtype, device="cuda")
+class _ServingRig:
+    """Device-resident 4096^2 source images (one per dtype and channel
+    count; a request is a window of one, row stride = the resident image's),
+    and a ring of output slots of the largest request's size."""
+
+    def __init__(self, nslots=128):
+        import torch
+        import synthimg
+        fields = [synthimg.one_over_f(4096, 4096, 48 + c) for c in range(3)]
+        self.resident = {}
+        for dt in ("u8", "f32"):
+            for C in (1, 3):
+                self.resident[(dt, C)] = to_dev(np.stack([synthimg.to_dtype(f, dt) for f in fields[:C]], axis=-1), dt)
+        self.slot_bytes = 4096 * 4096 * 3 * 4
+        self.nslots = nslots
+        self.out = torch.empty(self.slot_bytes * nslots, dtype=torch.uint8, device="cuda")
+        self.arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+
+    def desc(self, r, i):
+        import paper_1107_4958_amd as rsg
+        src = self.resident[(r["dtype"], r["C"])]
         d = rsg.rsg_image_desc()
-        d.src, d.dst = src.data_ptr(), dst.data_ptr()
+        d.src = src.data_ptr()
+        d.dst = self.out.data_ptr() + (i % self.nslots) * self.slot_bytes
         d.H, d.W, d.C = r["H"], r["W"], r["C"]
         d.src_stride, d.dst_stride = 4096 * r["C"], 0
         d.dt = rsg.tensor_dtype_code(src)
         d.sigma, d.K, d.b = r["sigma"], r["K"], rsg.RSG_REPLICATE
-        dsts.append(dst)
-        descs.append(d)
-    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
-    torch.cuda.synchronize()
-    cfg = rsg.rsg_server_config()
-    cfg.d_arena, cfg.arena_bytes = arena.data_ptr(), arena.numel()
-    cfg.hbm_budget = 16 << 30
-    cfg.max_inflight, cfg.n_streams, cfg.queue_depth, cfg.max_batch = 8, 4, 1024, 16
-    srv = rsg.rsg_server_create(cfg)
-    tickets = {}
-    stats = {}
-    busy = 0
-    try:
-        t0 = time.perf_counter()
-        i = 0
-        while len(stats) < n:
-            now = time.perf_counter() - t0
-            while i < n and reqs[i]["t_arrive"] <= now:
-                try:
-                    tickets[rsg.rsg_submit(srv, descs[i])] = i
+        return d
+
+    def run(self, reqs, open_loop=True, timeout_s=120.0):
+        """Submit reqs at their arrival times (or all at once), poll to
+        completion; per-request (submit, done) ns.  A request reuses an
+        output slot only after the request that held it has completed."""
+        import paper_1107_4958_amd as rsg
+        cfg = rsg.rsg_server_config()
+        cfg.d_arena, cfg.arena_bytes = self.arena.data_ptr(), self.arena.numel()
+        cfg.hbm_budget = 16 << 30
+        cfg.max_inflight, cfg.n_streams, cfg.queue_depth, cfg.max_batch = 8, 4, 1024, 16
+        srv = rsg.rsg_server_create(cfg)
+        n = len(reqs)
+        ticket = [None] * n
+        stats = [None] * n
+        busy = 0
+        try:
+            t0 = time.perf_counter()
+            i = 0
+            done = 0
+            pending = []
+            while done < n:
+                now = time.perf_counter() - t0
+                while i < n and (not open_loop or reqs[i]["t_arrive"] <= now):
+                    if i >= self.nslots and stats[i - self.nslots] is None:
+                        break                                      # its output slot is still in use
+                    try:
+                        ticket[i] = rsg.rsg_submit(srv, self.desc(reqs[i], i))
+                    except rsg.RsgError as e:
+                        if e.code != rsg.RSG_EBUSY:
+                            raise
+                        busy += 1
+                        break
+                    pending.append(i)
                     i += 1
-                except rsg.RsgError as e:
-                    if e.code != rsg.RSG_EBUSY:
-                        raise
-                    busy += 1
-                    break
-            for t in [t for t in tickets if tickets[t] not in stats]:
-                st = rsg.rsg_poll(srv, t)
-                if st.done:
-                    stats[tickets[t]] = (st.status, st.t_submit_ns, st.t_done_ns)
-            if now > 120:
-                raise RuntimeError("serving run did not finish in 120 s")
-    finally:
-        rsg.rsg_server_destroy(srv)
-    lat = np.array([(v[2] - v[1]) * 1e-6 for v in stats.values()])
-    assert all(v[0] == rsg.RSG_OK for v in stats.values())
-    span = (max(v[2] for v in stats.values()) - min(v[1] for v in stats.values())) * 1e-9
-    px = sum(r["H"] * r["W"] for r in reqs)
-    return {"requests": n, "qps_offered": qps, "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3), "gpix_s": round(px / span / 1e9, 2),
-            "ebusy_retries": busy, "max_inflight_launches": cfg.max_inflight, "max_batch": cfg.max_batch}
+                still = []
+                for j in pending:
+                    st = rsg.rsg_poll(srv, ticket[j])
+                    if st.done:
+                        if st.status != rsg.RSG_OK:
+                            raise RuntimeError("request %d failed with %d" % (j, st.status))
+                        stats[j] = (st.t_submit_ns, st.t_done_ns)
+                        done += 1
+                    else:
+                        still.append(j)
+                pending = still
+                if now > timeout_s:
+                    raise RuntimeError("serving run did not finish in %.0f s" % timeout_s)
+        finally:
+            rsg.rsg_server_destroy(srv)
+        lat = np.array([(d - s_) * 1e-6 for s_, d in stats])
+        span = (max(d for _, d in stats) - min(s_ for s_, _ in stats)) * 1e-9
+        px = sum(r["H"] * r["W"] for r in reqs)
+        return lat, span, px, busy
+
+
+def serving_workload(n=10000, fractions=(0.25, 0.5, 0.8, 0.95)):
+    """Poisson request streams (sides uniform in [128, 4096], C in {1, 3},
+    uint8 or FP32, sigma log-uniform in [0.5, 50], K in {3, 5}) served with
+    continuous batching under an HBM budget.  Saturation is the completion
+    rate of a closed burst; then open-loop streams at fractions of it.
+    Latency = done - submit per request (images device-resident)."""
+    import synthimg
+    rig = _ServingRig()
+    burst = synthimg.request_stream(min(n, 2000), 1e9, seed=6)
+    _, span, _, _ = rig.run(burst, open_loop=False)
+    sat = len(burst) / span
+    out = {"saturation_qps": round(sat, 1), "requests_per_rate": n, "rates": []}
+    for f in fractions:
+        reqs = synthimg.request_stream(n, f * sat, seed=5)
+        lat, span, px, busy = rig.run(reqs)
+        out["rates"].append({"fraction_of_saturation": f, "qps": round(f * sat, 1),
+                             "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                             "gpix_s": round(px / span / 1e9, 2), "ebusy_retries": busy})
+    return out
 
 
 def main():
@@ -392,8 +458,10 @@ def main():
     if not args.quick:
         print("bench: sigma x K grid", file=sys.stderr, flush=True)
         result["sigma_K_grid_4096"] = sigma_k_grid(imgs, max(20, args.steps // 4))
+        print("bench: plain 512^2", file=sys.stderr, flush=True)
+        result["plain_512"] = plain_workload(200)
         print("bench: batch", file=sys.stderr, flush=True)
-        result["batch"] = batch_workload(5)
+        result["batch"] = batch_workload(5, gpx if args.dtype == "f32" else None)
         print("bench: precision", file=sys.stderr, flush=True)
         result["precision_8192"] = precision_workload(10)
         print("bench: serving", file=sys.stderr, flush=True)

@@ -82,8 +82,9 @@ def _load():
         lib.orc_gauss_f64.argtypes = [P, I, I, I, D, I, P]
         lib.orc_box_f64_points.argtypes = [P, I, I, I, I, P, P, I, I, P, P, P, P]
         lib.orc_box_u8_points.argtypes = [P, I, I, I, I, P, P, ctypes.c_int64, I, I, P, P, P, P]
+        lib.orc_gauss_f64_points.argtypes = [P, I, I, I, D, I, I, P, P, P, P]
         for f in ("orc_eval_partition", "orc_fit", "orc_scale", "orc_quant_u8", "orc_box_f64",
-                  "orc_box_u8", "orc_gauss_f64", "orc_box_f64_points", "orc_box_u8_points"):
+                  "orc_box_u8", "orc_gauss_f64", "orc_box_f64_points", "orc_box_u8_points", "orc_gauss_f64_points"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -211,6 +212,21 @@ def gauss_filter(img: np.ndarray, sigma: float, boundary: int = REPLICATE) -> np
     if rc != 0:
         raise ValueError("orc_gauss_f64 failed")
     return dst
+
+
+def gauss_filter_points(img: np.ndarray, sigma: float, ys, xs, cs=None, boundary: int = REPLICATE):
+    """orc_gauss_f64 evaluated only at the listed output positions."""
+    H, W, C = _check_img(img)
+    src = np.ascontiguousarray(img, dtype=np.float64)
+    ys = np.ascontiguousarray(ys, dtype=np.int64)
+    xs = np.ascontiguousarray(xs, dtype=np.int64)
+    cs = np.zeros_like(ys) if cs is None else np.ascontiguousarray(cs, dtype=np.int64)
+    out = np.zeros(len(ys), dtype=np.float64)
+    rc = _load().orc_gauss_f64_points(_ptr(src), H, W, C, float(sigma), boundary, len(ys), _ptr(ys), _ptr(xs),
+                                      _ptr(cs), _ptr(out))
+    if rc != 0:
+        raise ValueError("orc_gauss_f64_points failed")
+    return out
 
 
 def box_filter_points(img: np.ndarray, r, w, ys, xs, cs=None, boundary: int = REPLICATE):

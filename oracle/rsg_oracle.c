@@ -22,7 +22,8 @@
  *   orc_box_u8     the same in exact integers, rounded once at the end.
  *   orc_gauss_f64  direct separable convolution with the sampled Gaussian
  *                  (the accuracy reference that replaces an exact library
- *                  Gaussian).
+ *                  Gaussian); orc_gauss_f64_points: the same at listed
+ *                  output positions.
  *
  * Readings taken where the paper is silent or garbled:
  *   - slice weights w_i = c_i - c_{i+1} (c_{k+1} = 0): the printed index runs
@@ -547,5 +548,40 @@ int orc_box_u8_points(const uint8_t* src, int H, int W, int C, int k, const int*
         }
         out[pidx] = (uint8_t)((acc + G2 / 2) / G2);
     }
+    return 0;
+}
+
+/* The sampled-Gaussian reference at a list of output positions only: the
+ * same separable sums as orc_gauss_f64 (|t| <= ceil(6 sigma), normalised
+ * taps), evaluated directly around each point. */
+int orc_gauss_f64_points(const double* src, int H, int W, int C, double sigma, int boundary, int npts,
+                         const int64_t* ys, const int64_t* xs, const int64_t* cs, double* out)
+{
+    if (H < 1 || W < 1 || C < 1 || !(sigma > 0.0)) return -1;
+    int R = (int)ceil(6.0 * sigma);
+    double* g = (double*)malloc(sizeof(double) * (2 * (size_t)R + 1));
+    if (!g) return -1;
+    double z = 0.0;
+    for (int t = -R; t <= R; ++t) { g[t + R] = exp(-(double)t * t / (2.0 * sigma * sigma)); z += g[t + R]; }
+    for (int t = 0; t <= 2 * R; ++t) g[t] /= z;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int pidx = 0; pidx < npts; ++pidx) {
+        int y = (int)ys[pidx], x = (int)xs[pidx], c = (int)cs[pidx];
+        double acc = 0.0;
+        for (int b = -R; b <= R; ++b) {
+            int in;
+            int yy = orc_ext(y + b, H, boundary, &in);
+            if (!in) continue;
+            double row = 0.0;
+            for (int a = -R; a <= R; ++a) {
+                int in2;
+                int xx = orc_ext(x + a, W, boundary, &in2);
+                if (in2) row += g[a + R] * src[((size_t)yy * W + xx) * C + c];
+            }
+            acc += g[b + R] * row;
+        }
+        out[pidx] = acc;
+    }
+    free(g);
     return 0;
 }

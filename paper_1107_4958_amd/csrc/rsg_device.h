@@ -205,6 +205,19 @@ __device__ __forceinline__ uint32_t exact_round_div(uint64_t U, const ImgParams&
     return exact_round_div_u(U, ip.G2, ip.G2half, ip.invG2);
 }
 
+// The same in FP64 for U < 2^53 given exactly as a double (sum of FP64
+// products that are all exact): quotient estimate from the reciprocal, then
+// one exact remainder N - q G^2 (an FMA) decides a +-1 correction.
+__device__ __forceinline__ uint32_t exact_round_div_f64(double U, double G2, double G2half, double invG2)
+{
+    const double N = U + G2half;                       // exact: < 2^53
+    double q = floor(N * invG2);
+    const double r = fma(-q, G2, N);                   // exact remainder
+    q += (r >= G2) ? 1.0 : 0.0;
+    q -= (r < 0.0) ? 1.0 : 0.0;
+    return uint32_t(q);
+}
+
 // One element at byte offset `boff` of a buffer, as float.
 template <class Tr>
 __device__ __forceinline__ float Tr_load_one(__amdgpu_buffer_rsrc_t rs, int boff)
@@ -490,10 +503,14 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         for (int j = 0; j < G; ++j) {
             const int voff = int(og + uint32_t(j) * dstr);
             if constexpr (kInt) {
-                uint64_t U = 0;
+                // U = sum m_k D_k < 2^52: every product and partial sum is an
+                // exact FP64 value, and FP64 FMAs run at the FP32 rate here
+                double U = 0.0;
 #pragma unroll
-                for (int k = 0; k < KT; ++k) U += uint64_t(wm[k]) * uint32_t(rv[j][2 * k] - rv[j][2 * k + 1]);
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, voff, 0, 0);
+                for (int k = 0; k < KT; ++k)
+                    U = fma(double(wm[k]), double(uint32_t(rv[j][2 * k] - rv[j][2 * k + 1])), U);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div_f64(U, ip.G2d, ip.G2halfd, ip.invG2d)),
+                                                     rs_dst, voff, 0, 0);
             } else {
                 float o = c2dc;
 #pragma unroll

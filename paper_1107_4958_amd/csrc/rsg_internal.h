@@ -44,6 +44,7 @@ struct ImgParams {
     uint64_t G2;                   // G^2 (uint8 rounding denominator)
     uint64_t G2half;               // floor(G^2 / 2)
     float invG2;                   // 1 / G^2 rounded to FP32 (quotient estimate)
+    double G2d, G2halfd, invG2d;   // the same in FP64 (exact: G^2 < 2^48)
     int32_t R;                     // max r
     // tile plan
     int32_t seg;                   // lanes per row in the row scan (16, 32, 64)
@@ -82,6 +83,7 @@ struct PassParams {
     float dc32;
     uint64_t G2, G2half;
     float invG2;
+    double G2d, G2halfd, invG2d;
     int32_t boundary;
     int32_t vec;                   // rows allow 16-byte chunk loads
     int32_t win_pitch;             // LDS words per wave window

@@ -165,6 +165,9 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         p.G2 = b.G * b.G;
         p.G2half = p.G2 / 2;
         p.invG2 = float(1.0 / double(p.G2));
+        p.G2d = double(p.G2);
+        p.G2halfd = double(p.G2half);
+        p.invG2d = 1.0 / p.G2d;
     }
 
     // taps: K < 3 is padded with zero-weight boxes of half-width 0

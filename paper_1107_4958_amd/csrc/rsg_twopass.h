@@ -223,10 +223,11 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
                 for (int kk = 0; kk < KT; ++kk) s += __umul24(wm[kk], win[o + tp[kk]] - win[o + tm[kk]]);
                 word = s;
             } else if constexpr (OUT == kOutU8) {
-                uint64_t U = 0;
+                double U = 0.0;                       // exact: see the fused kernel
 #pragma unroll
-                for (int kk = 0; kk < KT; ++kk) U += uint64_t(wm[kk]) * uint32_t(win[o + tp[kk]] - win[o + tm[kk]]);
-                word = exact_round_div_u(U, p.G2, p.G2half, p.invG2);
+                for (int kk = 0; kk < KT; ++kk)
+                    U = fma(double(wm[kk]), double(uint32_t(win[o + tp[kk]] - win[o + tm[kk]])), U);
+                word = exact_round_div_f64(U, p.G2d, p.G2halfd, p.invG2d);
             } else {
                 float s = offo[t] * dc;
 #pragma unroll

@@ -209,3 +209,13 @@ def test_metrics():
     y = ref + 1.0
     assert abs(oracle.nrms(y, ref) - 0.01) < 1e-15
     assert abs(oracle.psnr(y, ref) - (-10 * math.log10((1 / 255) ** 2))) < 1e-12
+
+
+def test_gauss_points_match_full_filter():
+    img = synthimg.image(70, 90, 3, "f32", seed=5).astype(np.float64)
+    rng = np.random.default_rng(2)
+    ys, xs, cs = rng.integers(0, 70, 200), rng.integers(0, 90, 200), rng.integers(0, 3, 200)
+    for boundary in (oracle.REPLICATE, oracle.ZERO):
+        full = oracle.gauss_filter(img, 3.5, boundary)
+        pts = oracle.gauss_filter_points(img, 3.5, ys, xs, cs, boundary=boundary)
+        assert np.max(np.abs(pts - full[ys, xs, cs])) <= 1e-9
