@@ -204,13 +204,15 @@ int rsg_plan_shape(const rsg_image_desc* d, int32_t* seg_height, int32_t* tasks,
 int rsg_tune_override(int32_t seg_height);
 
 /* Process-wide choice of kernel path for every later plan: 0 lets the
- * planner choose (two passes for wide boxes, R * C >= 40, when they fit),
- * 1 forces the fused single-launch kernel, 2 forces the two-pass path (row
+ * planner choose (the tuning table, else two passes for wide boxes,
+ * R * C >= 40, when they fit), 1 forces the fused single-launch kernel (two
+ * waves per task: row pass and column pass), 2 forces the two-pass path (row
  * filter into an FP32 / uint32 intermediate stored transposed, then the same
  * on the intermediate; the intermediate, 4 H W C bytes, is allocated and
- * released in stream order).  Results agree to FP32 rounding and are
- * bit-identical for uint8.  For the autotuner and tests.
- * Errors: RSG_EINVAL (path not 0, 1 or 2); later plans return
+ * released in stream order), 3 forces the fused kernel with one wave per
+ * task (the form batched launches use).  Results agree to FP32 rounding and
+ * are bit-identical for uint8.  For the autotuner and tests.
+ * Errors: RSG_EINVAL (path not in 0..3); later plans return
  * RSG_EUNSUPPORTED when the forced path cannot hold the boxes. */
 int rsg_tune_path(int32_t path);
 

@@ -228,7 +228,7 @@ def rsg_tune_override(seg_height: int) -> None:
     _check(_lib.rsg_tune_override(int(seg_height)))
 
 
-RSG_PATH_AUTO, RSG_PATH_FUSED, RSG_PATH_TWO_PASS = 0, 1, 2
+RSG_PATH_AUTO, RSG_PATH_FUSED, RSG_PATH_TWO_PASS, RSG_PATH_FUSED_ONE_WAVE = 0, 1, 2, 3
 
 
 def rsg_tune_path(path: int) -> None:

@@ -75,7 +75,8 @@ int rsg_plan_shape(const rsg_image_desc* d, int32_t* seg_height, int32_t* tasks,
 int rsg_tune_path(int32_t path)
 {
     using namespace rsg;
-    if (path < 0 || path > 2) return set_error(RSG_EINVAL, "path must be 0 (planner), 1 (fused) or 2 (two-pass)");
+    if (path < 0 || path > 3)
+        return set_error(RSG_EINVAL, "path must be 0 (planner), 1 (fused), 2 (two-pass) or 3 (fused, one wave per task)");
     set_path_override(path);
     return RSG_OK;
 }

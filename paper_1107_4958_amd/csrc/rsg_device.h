@@ -383,7 +383,6 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     float c2dc = 0.0f;
     int slot0 = 0;                             // ring slot of the first row of the queued group
     Acc Tq[G];                                 // row-pass result of the group queued for the column pass
-    float kq = 0.0f;                           // its offset correction (float types)
 
     // Row pass, first half: consume the group's chunk, reuse its registers
     // for the load of group g + PF (so the loop-carried buffers are written
@@ -443,7 +442,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
             }
         }
     };
-    auto row_combine = [&](const Taps& pv, Acc (&T)[G]) {
+    auto row_combine = [&](const Taps& pv, Acc (&T)[G], float init) {
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             Acc t;
@@ -452,7 +451,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 #pragma unroll
                 for (int k = 0; k < KT; ++k) t += __umul24(wm[k], pv[j][2 * k] - pv[j][2 * k + 1]);
             } else {
-                t = wf[0] * (pv[j][0] - pv[j][1]);
+                t = fmaf(wf[0], pv[j][0] - pv[j][1], init);
 #pragma unroll
                 for (int k = 1; k < KT; ++k) t = fmaf(wf[k], pv[j][2 * k] - pv[j][2 * k + 1], t);
             }
@@ -461,16 +460,17 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     };
 
     // Column pass, first half: running sums down the columns (Eq. alg1) of
-    // the queued group into the ring.  Float types add each row as
-    // (T + off * dc) - c2: the offset restores the row's true box sums, c2
-    // keeps the column sums small.
+    // the queued group into the ring.  Float types enter each row as
+    // (T + off * dc) - c2, folded into the row combine: the offset restores
+    // the row's true box sums, c2 keeps the column sums small.  (The
+    // two-wave form computes exactly the same values, so batched and single
+    // launches agree bit for bit.)
     auto col_push = [&]() {
         const int wbase = slot0 * RP + lane;
         const int mbase = (slot0 == 0 ? L : slot0) * RP + lane;
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            if constexpr (kInt) colacc += Tq[j];
-            else colacc += Tq[j] + kq;
+            colacc += Tq[j];
             ring[wbase + j * RP] = colacc;
             ring[mbase + j * RP] = colacc;          // mirror copy (same slot unless slot0 == 0)
         }
@@ -546,12 +546,14 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     {   // step 0: group 1's row scan, group 0's row differences and column sums
         const float off_next = row_scan(1, buf[1 % PF], 1);
         Acc T[G];
-        row_combine(pv, T);
+        float init = 0.0f;
+        if constexpr (!kInt) init = off_cur * dc - c2;     // c2 = 0 here: the first row's true value
+        row_combine(pv, T, init);
         if constexpr (!kInt) {
-            const float odc = off_cur * dc;
-            c2 = T[0] + odc;
+            c2 = T[0];
             c2dc = c2 * dc;
-            kq = odc - c2;
+#pragma unroll
+            for (int j = 0; j < G; ++j) T[j] -= c2;
         }
         dropped_stores(PF * G + G);
 #pragma unroll
@@ -568,14 +570,15 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         for (int b = 0; b < PF; ++b) {
             const int gg = g + b;
             const float off_next = row_scan(gg + 1, buf[(2 + b) % PF], b & 1);
+            float init = 0.0f;
+            if constexpr (!kInt) init = off_cur * dc - c2;
             Acc T[G];
-            row_combine(pv, T);
+            row_combine(pv, T, init);
             col_combine(gg - 1, rv);
             slot0 += G;
             slot0 -= (slot0 >= L) ? L : 0;
 #pragma unroll
             for (int j = 0; j < G; ++j) Tq[j] = T[j];
-            if constexpr (!kInt) kq = off_cur * dc - c2;
             col_push();
             wave_lds_fence();
             row_reads(pv, b & 1);                // tile of group gg + 1
@@ -585,8 +588,242 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     }
 }
 
+// --------------------------------------------------------------------------
+// Producer / consumer form of the streaming loop: one task per workgroup of
+// two waves.  Wave 0 runs the row pass of every group (loads, running sums,
+// row box differences) and hands the group's row results to wave 1 through a
+// two-slot LDS queue; wave 1 runs the column pass (running column sums in the
+// ring, column box differences, stores).  One workgroup barrier per group
+// passes a queue slot: at barrier g slot g & 1 holds group g, and the slot
+// wave 0 fills next was read by wave 1 before it reached barrier g.  Both
+// waves take the same number of barriers.  The split doubles the waves per
+// task without adding halo rows, and each wave's chain of dependent LDS round
+// trips is half as long.
+// --------------------------------------------------------------------------
+template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE>
+__device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
+{
+    using Acc = typename Tr::Acc;
+    constexpr bool kInt = Tr::kInt;
+    constexpr int G = kWave / SEG;
+    constexpr int PW = SEG * NPL;
+    constexpr int PP = row_tile_pitch(SEG, NPL);
+    constexpr int RP = kWave;
+    constexpr int PF = kPrefetch;
+    constexpr int es = Tr::kSize;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int R = ip.R;
+    const int L = ip.L;
+    const int H = ip.H;
+    const int W = ip.W;
+    const int WC = W * C;
+    const bool replicate = (ip.boundary == RSG_REPLICATE);
+    static_assert(PW <= PP, "tile pitch");
+
+    // LDS: [row tile G x PP][queue 2 x G x 64][column offsets 64][ring (L + G) x 64]
+    Acc* P = reinterpret_cast<Acc*>(lds);
+    Acc* Q = P + G * PP;
+    float* c2s = reinterpret_cast<float*>(Q + 2 * G * kWave);
+    Acc* ring = reinterpret_cast<Acc*>(c2s + kWave);
+
+    const int ngroups = (tg.niter + G - 1) / G;
+    const int nsteps = (ngroups + PF - 1) / PF * PF;    // both waves: one barrier per step
+    const float dc = ip.dc32;
+    float wf[KT];
+    uint32_t wm[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        wf[k] = ip.wf[k];
+        wm[k] = ip.m[k];
+    }
+    const int64_t sstride = ip.src_stride * es;
+    const int64_t dstride = ip.dst_stride * es;
+
+    if (wave == 0) {
+        // ---------------- row pass ----------------
+        const int jrow = lane / SEG;
+        const int q = lane % SEG;
+        const int y_lo = max(0, tg.ybase);
+        const char* sbase = reinterpret_cast<const char*>(ip.src) + int64_t(y_lo) * sstride;
+        const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(H - 1 - y_lo) * sstride + int64_t(WC) * es);
+        const int cs = tg.a0 + NPL * q;
+        const int vec_voff = cs * es;
+        int eoff[EDGE ? NPL : 1];
+        if constexpr (EDGE) {
+            const int x0 = floor_div(cs, C);
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                const int x = x0 + i / C;
+                const int xc = x < 0 ? 0 : (x >= W ? W - 1 : x);
+                eoff[i] = (replicate || (x >= 0 && x < W)) ? (xc * C + i % C) * es : -1;
+            }
+        }
+        const int sstride32 = int(sstride);
+        auto load = [&](Chunk<Tr, NPL>& ch, int g) {
+            const int y = tg.ybase + g * G + jrow;
+            const int yc = y < 0 ? 0 : (y >= H ? H - 1 : y);
+            const bool zero_row = !replicate && yc != y;
+            const int rowoff = (yc - y_lo) * sstride32;
+            if constexpr (EDGE) {
+                int vo[NPL];
+#pragma unroll
+                for (int i = 0; i < NPL; ++i) vo[i] = (eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
+                load_chunk_elem<Tr, NPL>(ch, rs_src, vo, 0);
+            } else {
+                load_chunk_vec<Tr, NPL>(ch, rs_src, zero_row ? kDropOffset : vec_voff + rowoff, 0);
+            }
+        };
+        int tp[KT], tm[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            tp[k] = tg.off + lane + ip.r[k] * C;
+            tm[k] = tg.off + lane - (ip.r[k] + 1) * C;
+        }
+        Chunk<Tr, NPL> buf[PF];
+#pragma unroll
+        for (int b = 0; b < PF; ++b) {          // this wave issues loads only: every wait is exact
+            __builtin_amdgcn_sched_barrier(0);
+            load(buf[b], b);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        float c2 = 0.0f;
+        for (int g = 0; g < nsteps; g += PF) {
+#pragma unroll
+            for (int b = 0; b < PF; ++b) {
+                const int gg = g + b;
+                __builtin_amdgcn_sched_barrier(0);
+                Acc v[NPL];
+                float off = 0.0f;
+                if constexpr (!kInt) {
+                    off = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(buf[b].w, 0))));
+#pragma unroll
+                    for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i) - off;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                load(buf[b], gg + PF);
+                __builtin_amdgcn_sched_barrier(0);
+                // running sums along the row (Eq. alg1)
+#pragma unroll
+                for (int i = C; i < NPL; ++i) v[i] = v[i] + v[i - C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const Acc tot = v[NPL - C + c];
+                    const Acc ex = segment_inclusive_scan<SEG>(tot) - tot;
+#pragma unroll
+                    for (int i = c; i < NPL; i += C) v[i] = v[i] + ex;
+                }
+                using Acc4 = typename std::conditional<kInt, uint4, float4>::type;
+                Acc4* dst4 = reinterpret_cast<Acc4*>(P + jrow * PP + q * NPL);
+#pragma unroll
+                for (int h = 0; h < NPL / 4; ++h) {
+                    Acc4 t4;
+                    t4.x = v[4 * h]; t4.y = v[4 * h + 1]; t4.z = v[4 * h + 2]; t4.w = v[4 * h + 3];
+                    dst4[h] = t4;
+                }
+                wave_lds_fence();
+                // row box differences (Eq. indep), lane = column; floats add
+                // the group offset's share and subtract the column offset c2
+                float init = 0.0f;
+                if constexpr (!kInt) init = off * dc - c2;
+                Acc T[G];
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const Acc* Pj = P + j * PP;
+                    Acc t;
+                    if constexpr (kInt) {
+                        t = 0;
+#pragma unroll
+                        for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
+                    } else {
+                        t = fmaf(wf[0], Pj[tp[0]] - Pj[tm[0]], init);
+#pragma unroll
+                        for (int k = 1; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
+                    }
+                    T[j] = t;
+                }
+                if constexpr (!kInt) {
+                    if (gg == 0) {                   // column offset: the first row's true value
+                        c2 = T[0];
+#pragma unroll
+                        for (int j = 0; j < G; ++j) T[j] -= c2;
+                        c2s[lane] = c2;
+                    }
+                }
+                Acc* Qs = Q + (gg & 1) * G * kWave;
+#pragma unroll
+                for (int j = 0; j < G; ++j) Qs[j * kWave + lane] = T[j];
+                __syncthreads();
+            }
+        }
+    } else {
+        // ---------------- column pass ----------------
+        const char* dbase = reinterpret_cast<char*>(ip.dst) + int64_t(tg.y0) * dstride;
+        const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(dbase, int64_t(tg.hs - 1) * dstride + int64_t(WC) * es);
+        const int s = tg.s0 + lane;
+        const uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
+        const uint32_t dstr = uint32_t(dstride);
+        Acc colacc = Acc(0);
+        float c2dc = 0.0f;
+        int slot0 = 0;
+        for (int g = 0; g < nsteps; ++g) {
+            __syncthreads();
+            if constexpr (!kInt) {
+                if (g == 0) c2dc = c2s[lane] * dc;
+            }
+            const Acc* Qs = Q + (g & 1) * G * kWave;
+            const int wbase = slot0 * RP + lane;
+            const int mbase = (slot0 == 0 ? L : slot0) * RP + lane;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                colacc += Qs[j * kWave + lane];
+                ring[wbase + j * RP] = colacc;
+                ring[mbase + j * RP] = colacc;
+            }
+            wave_lds_fence();
+            Acc rv[G][2 * KT];
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                int a = slot0 - R + ip.r[k];
+                int b = slot0 - R - ip.r[k] - 1;
+                a += (a < 0) ? L : 0;
+                b += (b < 0) ? L : 0;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    rv[j][2 * k] = ring[a * RP + lane + j * RP];
+                    rv[j][2 * k + 1] = ring[b * RP + lane + j * RP];
+                }
+            }
+            const int it0 = g * G;
+            const uint32_t og = (it0 >= tg.emit0) ? ocol + uint32_t(it0 - tg.emit0) * dstr : uint32_t(kDropOffset);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int voff = int(og + uint32_t(j) * dstr);
+                if constexpr (kInt) {
+                    double U = 0.0;
+#pragma unroll
+                    for (int k = 0; k < KT; ++k)
+                        U = fma(double(wm[k]), double(uint32_t(rv[j][2 * k] - rv[j][2 * k + 1])), U);
+                    __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div_f64(U, ip.G2d, ip.G2halfd, ip.invG2d)),
+                                                         rs_dst, voff, 0, 0);
+                } else {
+                    float o = c2dc;
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) o = fmaf(wf[k], rv[j][2 * k] - rv[j][2 * k + 1], o);
+                    store_out<Tr>(rs_dst, voff, 0, o);
+                }
+            }
+            slot0 += G;
+            slot0 -= (slot0 >= L) ? L : 0;
+        }
+    }
+}
+
 // One task: 64 sample-columns x hs output rows of image `ip`.
-template <class Tr, int C, int SEG, int NPL, int KT>
+template <class Tr, int C, int SEG, int NPL, int KT, bool PC = false>
 __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t* lds)
 {
     constexpr int G = kWave / SEG;
@@ -604,8 +841,13 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
     tg.ybase = tg.y0 - ip.R - 1 - pre;
     const int WC = ip.W * C;
     const bool interior = ip.vec && tg.a0 >= 0 && tg.a0 + SEG * NPL <= WC;
-    if (interior) stream_task<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
-    else stream_task<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
+    if constexpr (PC) {
+        if (interior) stream_task_pc<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
+        else stream_task_pc<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
+    } else {
+        if (interior) stream_task<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
+        else stream_task<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
+    }
 }
 
 // Task order: blocks are dealt to the 8 XCDs round-robin; give each XCD a
@@ -618,6 +860,14 @@ __device__ __forceinline__ int xcd_task(int b, int n)
     const int q = n / kXcds;
     const int rem = n % kXcds;
     return x * q + min(x, rem) + i;
+}
+
+// One task per workgroup of two waves (row-pass and column-pass waves).
+template <class Tr, int C, int SEG, int NPL, int KT>
+__global__ __launch_bounds__(2 * kWave) void k_single_pc(ImgParams ip)
+{
+    extern __shared__ uint32_t lds[];
+    run_task<Tr, C, SEG, NPL, KT, true>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
 }
 
 template <class Tr, int C, int SEG, int NPL, int KT>

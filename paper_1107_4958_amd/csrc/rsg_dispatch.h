@@ -27,6 +27,13 @@ inline int set_lds_limit(const void* fn, uint32_t bytes)
 template <class Tr, int C, int SEG, int NPL, int KT>
 int launch_one(const ImgParams& ip, hipStream_t st)
 {
+    if (ip.pc) {
+        auto fn = dev::k_single_pc<Tr, C, SEG, NPL, KT>;
+        int rc = set_lds_limit(reinterpret_cast<const void*>(fn), ip.lds_bytes);
+        if (rc != RSG_OK) return rc;
+        hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3(2 * kWave), ip.lds_bytes, st, ip);
+        return RSG_OK;
+    }
     auto fn = dev::k_single<Tr, C, SEG, NPL, KT>;
     int rc = set_lds_limit(reinterpret_cast<const void*>(fn), ip.lds_bytes);
     if (rc != RSG_OK) return rc;

@@ -56,9 +56,11 @@ struct ImgParams {
     int32_t vec;                   // 1: rows allow vector loads of one chunk
     int32_t nstrips, nsegs, ntasks;
     int32_t variant;               // kernel instantiation
-    uint32_t lds_bytes;            // dynamic LDS per wave
+    uint32_t lds_bytes;            // dynamic LDS per workgroup of a single launch
+    uint32_t lds_one;              // dynamic LDS of the one-wave fused form (batches, serving)
     // two-pass path (wide boxes): row filter + transposed store, twice
     int32_t path;                  // kPathFused or kPathTwoPass
+    int32_t pc;                    // fused path: 1 = producer / consumer workgroups of two waves
     int32_t pnpl[2];               // samples per lane of pass A, pass B
     int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
     uint32_t plds[2];              // LDS bytes per workgroup of pass A, pass B
@@ -171,6 +173,13 @@ inline void scan_layout(int C, int i, int* seg, int* npl)
 // 32 (mod 64) words puts the pair in opposite halves of the 64 banks.  The
 // column ring keeps the dense 64-word pitch (one word per lane).
 constexpr int row_tile_pitch(int seg, int npl) { return seg * npl + 32; }
+// Producer / consumer form: one row tile, a two-slot queue of G rows, the
+// column offsets and the ring of L + G rows.
+inline uint32_t tile_lds_bytes_pc(int seg, int npl, int L)
+{
+    const int G = kWave / seg;
+    return uint32_t(4 * (G * row_tile_pitch(seg, npl) + 2 * G * kWave + kWave + (L + G) * kWave));
+}
 // Two row tiles (double-buffered) and the ring of L + G rows.
 inline uint32_t tile_lds_bytes(int seg, int npl, int L)
 {

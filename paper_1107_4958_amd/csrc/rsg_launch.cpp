@@ -222,7 +222,7 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         b.C = std::get<1>(kv.first);
         b.kt = std::get<2>(kv.first);
         b.lds = 0;
-        for (const BatchTask& t : kv.second) b.lds = std::max(b.lds, h_imgs[t.img].lds_bytes);
+        for (const BatchTask& t : kv.second) b.lds = std::max(b.lds, h_imgs[t.img].lds_one);   // one-wave kernel
         // resident waves per CU are bounded by LDS (160 KiB per CU on gfx950)
         int per_cu = b.lds ? int((160u * 1024u) / b.lds) : 16;
         per_cu = std::max(1, std::min(per_cu, 16));

@@ -192,7 +192,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     int hs_t = 0;
     const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t);
     bool two = two_ok && (tabled ? hs_t < 0 : R * C >= kTwoPassMinRC);
-    if (ov == 1) two = false;
+    if (ov == 1 || ov == 3) two = false;
     if (ov == 2) {
         if (!two_ok) return set_error(RSG_EUNSUPPORTED, "two-pass path: box half-width %d too wide for C=%d", R, C);
         two = true;
@@ -211,7 +211,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         if (span <= int64_t(sg) * n) { seg = sg; npl = n; align = al; }
     }
     if (!seg && !two) {
-        if (two_ok && ov != 1) {
+        if (two_ok && ov != 1 && ov != 3) {
             two = true;
         } else {
             int sg, n;
@@ -241,9 +241,16 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     }
     p.G = kWave / seg;
     p.L = (2 * R + 1 + p.G + p.G - 1) / p.G * p.G;
-    p.lds_bytes = tile_lds_bytes(seg, npl, p.L);
-    if (p.lds_bytes > kLdsLimit)
-        return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", p.lds_bytes, kLdsLimit);
+    // single launches run each task on two waves (row pass / column pass);
+    // path override 3 keeps the one-wave form (the one the batch kernel uses)
+    // (batched and served images always run the one-wave form, so a plan is
+    // only valid when that form fits too)
+    p.pc = (ov == 3) ? 0 : 1;
+    p.lds_one = tile_lds_bytes(seg, npl, p.L);
+    p.lds_bytes = p.pc ? tile_lds_bytes_pc(seg, npl, p.L) : p.lds_one;
+    if (std::max(p.lds_bytes, p.lds_one) > kLdsLimit)
+        return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", std::max(p.lds_bytes, p.lds_one),
+                         kLdsLimit);
     p.nstrips = int((WC + kWave - 1) / kWave);
 
     // ---- segment height ----
@@ -258,7 +265,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         };
         while (hs > 1 && !fits(hs)) hs = (hs + 1) / 2;
         if (!fits(hs)) {
-            if (two_ok && ov != 1) return finish_two_pass();     // it addresses every row on its own
+            if (two_ok && ov != 1 && ov != 3) return finish_two_pass();     // it addresses every row on its own
             return set_error(RSG_EUNSUPPORTED, "row stride too large for a tile (%lld bytes, box half-width %d)",
                              (long long)stride_b, R);
         }

@@ -204,3 +204,18 @@ def test_paths_agree(dtype):
         assert np.array_equal(outs[0], outs[1])
     else:
         assert rel_max_err(outs[1], outs[0].astype(np.float64)) <= FP32_TOL
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+@pytest.mark.parametrize("H,W,C,sigma,K,boundary", [(200, 333, 1, 8.0, 3, 0), (97, 250, 2, 4.0, 4, 1),
+                                                    (61, 211, 3, 6.0, 5, 0), (33, 520, 1, 0.5, 5, 1)])
+def test_one_wave_fused_form(dtype, H, W, C, sigma, K, boundary):
+    """The fused kernel with one wave per task (the form batched launches
+    run) forced for single images."""
+    import paper_1107_4958_amd as rsg
+    img = synthimg.image(H, W, C, dtype, 47)
+    rsg.rsg_tune_path(rsg.RSG_PATH_FUSED_ONE_WAVE)
+    try:
+        _check(img, dtype, sigma, K, boundary)
+    finally:
+        rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)

@@ -118,7 +118,7 @@ def test_wide_boxes_take_the_two_pass_path():
         "assert rsg.rsg_plan_shape(_desc(8192, 8192, sigma=64.0, K=5))[0] < 8192\n"
         "rsg.rsg_tune_path(rsg.RSG_PATH_TWO_PASS)\n"
         "assert rsg.rsg_plan_shape(_desc(64, 64, sigma=1.0, K=3))[0] == 64\n"
-        "with pytest.raises(rsg.RsgError):\n    rsg.rsg_tune_path(3)\n")
+        "with pytest.raises(rsg.RsgError):\n    rsg.rsg_tune_path(4)\n")
     R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
     _run_planner_code("assert rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))[0] == 4096\n",
                       "1 1 %d %d 0 %d -1\n" % (R, R, 1 << 40))
