@@ -901,5 +901,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     }
 }
 
+// Persistent batch kernel, two-wave form: each workgroup pops (image, task)
+// items and runs them as a row-pass / column-pass pair.  LDS word 0 carries
+// the popped index to both waves; the task's LDS starts 16 bytes later.
+template <class Tr, int C, int KT, int S0, int N0, int S1, int N1, int S2, int N2, int S3, int N3>
+__global__ __launch_bounds__(2 * kWave) void k_batch_pc(const ImgParams* __restrict__ imgs,
+                                                       const BatchTask* __restrict__ tasks, int ntasks,
+                                                       unsigned* __restrict__ counter)
+{
+    extern __shared__ uint32_t lds[];
+    uint32_t* tl = lds + kBatchSlotWords;
+    for (;;) {
+        if (threadIdx.x == 0) lds[0] = atomicAdd(counter, 1u);
+        __syncthreads();
+        const unsigned t = __builtin_amdgcn_readfirstlane(lds[0]);
+        if (t >= unsigned(ntasks)) break;                  // the same for both waves
+        const BatchTask bt = tasks[t];
+        const ImgParams& ip = imgs[bt.img];
+        if (ip.seg == S0 && ip.npl == N0) run_task<Tr, C, S0, N0, KT, true>(ip, bt.task, tl);
+        else if (ip.seg == S1 && ip.npl == N1) run_task<Tr, C, S1, N1, KT, true>(ip, bt.task, tl);
+        else if (ip.seg == S2 && ip.npl == N2) run_task<Tr, C, S2, N2, KT, true>(ip, bt.task, tl);
+        else if (ip.seg == S3 && ip.npl == N3) run_task<Tr, C, S3, N3, KT, true>(ip, bt.task, tl);
+        __syncthreads();                                   // both waves are done with the slot and the tiles
+    }
+}
+
 }  // namespace dev
 }  // namespace rsg

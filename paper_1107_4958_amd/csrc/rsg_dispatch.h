@@ -84,6 +84,14 @@ template <class Tr, int C, int KT>
 int batch_one(const BatchClassLaunch& b, hipStream_t st)
 {
     using Lo = Layouts<C>;
+    if (b.pc) {
+        auto fn = dev::k_batch_pc<Tr, C, KT, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2], Lo::N[2], Lo::S[3],
+                                  Lo::N[3]>;
+        int rc = set_lds_limit(reinterpret_cast<const void*>(fn), b.lds);
+        if (rc != RSG_OK) return rc;
+        hipLaunchKernelGGL(fn, dim3(b.grid), dim3(2 * kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks, b.d_counter);
+        return RSG_OK;
+    }
     auto fn = dev::k_batch<Tr, C, KT, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2], Lo::N[2], Lo::S[3], Lo::N[3]>;
     int rc = set_lds_limit(reinterpret_cast<const void*>(fn), b.lds);
     if (rc != RSG_OK) return rc;

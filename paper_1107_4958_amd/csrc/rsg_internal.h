@@ -145,6 +145,7 @@ inline uint32_t pass_lds_bytes(int npl, int hw, int stages)
 // One persistent launch over the tasks of one (dtype, C, kt) class.
 struct BatchClassLaunch {
     int dtype, C, kt;
+    int pc;                        // 1: two-wave workgroups (LDS includes the task slot)
     int grid;
     uint32_t lds;
     const ImgParams* d_imgs;
@@ -186,6 +187,9 @@ inline uint32_t tile_lds_bytes(int seg, int npl, int L)
     const int G = kWave / seg;
     return uint32_t(4 * (2 * G * row_tile_pitch(seg, npl) + (L + G) * kWave));
 }
+// The two-wave batch kernel passes each popped task index through the first
+// 16 bytes of LDS (which keeps the tiles 16-byte aligned).
+constexpr int kBatchSlotWords = 4;
 
 // h_stage: optional pinned host buffer of >= batch_workspace_bytes() used to
 // stage the work list (must not be reused before the copy has executed);

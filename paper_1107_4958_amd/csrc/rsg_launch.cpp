@@ -144,10 +144,10 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
     if (ws_bytes < need) return set_error(RSG_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, need);
 
     // fused images: group the tasks by kernel class, keeping their order
-    std::map<std::tuple<int, int, int>, std::vector<BatchTask>> classes;
+    std::map<std::tuple<int, int, int, int>, std::vector<BatchTask>> classes;
     for (int t = 0; t < ntasks; ++t) {
         const ImgParams& ip = h_imgs[h_tasks[t].img];
-        classes[std::make_tuple(ip.dtype, ip.C, ip.kt)].push_back(h_tasks[t]);
+        classes[std::make_tuple(ip.dtype, ip.C, ip.kt, ip.pc)].push_back(h_tasks[t]);
     }
 
     // two-pass images: one intermediate for all, pass parameters 2j (A) and
@@ -221,11 +221,16 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         b.dtype = std::get<0>(kv.first);
         b.C = std::get<1>(kv.first);
         b.kt = std::get<2>(kv.first);
+        b.pc = std::get<3>(kv.first);
         b.lds = 0;
-        for (const BatchTask& t : kv.second) b.lds = std::max(b.lds, h_imgs[t.img].lds_one);   // one-wave kernel
-        // resident waves per CU are bounded by LDS (160 KiB per CU on gfx950)
+        for (const BatchTask& t : kv.second) {
+            const ImgParams& ip = h_imgs[t.img];
+            b.lds = std::max(b.lds, b.pc ? ip.lds_bytes + 4 * kBatchSlotWords : ip.lds_one);
+        }
+        // resident workgroups per CU are bounded by LDS (160 KiB per CU on
+        // gfx950); extra workgroups only start late and find the list empty
         int per_cu = b.lds ? int((160u * 1024u) / b.lds) : 16;
-        per_cu = std::max(1, std::min(per_cu, 16));
+        per_cu = std::max(1, std::min(per_cu, b.pc ? 8 : 16));
         b.ntasks = int(kv.second.size());
         b.grid = std::max(1, std::min(b.ntasks, ncu * per_cu));
         b.d_imgs = reinterpret_cast<const ImgParams*>(ws + o_img);
