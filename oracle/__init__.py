@@ -44,6 +44,7 @@ PHI_DC = 16.5                # Section 4.1: completed DC value of the spectrum
 
 REPLICATE = 0
 ZERO = 1
+REFLECT = 2      # half-sample symmetric: ... c b a | a b c d | d c b ...
 
 _lock = threading.Lock()
 _lib = None

@@ -44,8 +44,10 @@
  *     product that is an integer in exact arithmetic is not lost to rounding;
  *   - Eq. scale2 is applied as printed and the weights are then normalised to
  *     unit DC gain;
- *   - boundaries: replicate (clamp) or zero extension; channels interleaved
- *     and filtered independently;
+ *   - boundaries (the paper names none): replicate (clamp), zero extension,
+ *     or reflect, the half-sample symmetric extension (... c b a | a b c d |
+ *     d c b ...) repeated with period 2n for boxes wider than the axis;
+ *     channels interleaved and filtered independently;
  *   - uint8 output: round half up of the exact rational U / G^2.
  */
 #include <math.h>
@@ -339,6 +341,15 @@ static inline int orc_ext(int i, int n, int boundary, int* inside)
 {
     if (i >= 0 && i < n) { *inside = 1; return i; }
     if (boundary == 0) { *inside = 1; return i < 0 ? 0 : n - 1; }   /* replicate */
+    if (boundary == 2) {                                           /* reflect */
+        /* half-sample symmetric extension: f(-1) = f(0), f(n) = f(n-1),
+         * repeated with period 2n so that any offset is defined */
+        int64_t p = 2 * (int64_t)n;
+        int64_t m = (int64_t)i % p;
+        if (m < 0) m += p;
+        *inside = 1;
+        return (int)(m < n ? m : p - 1 - m);
+    }
     *inside = 0;                                                   /* zero */
     return 0;
 }

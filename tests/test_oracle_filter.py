@@ -16,10 +16,17 @@ def _pad(img, R, mode):
     return np.pad(img, ((R, R), (R, R), (0, 0)), mode=mode)
 
 
+# numpy's padding modes for the oracle's boundaries; "symmetric" is the
+# half-sample reflection (d c b a | a b c d | d c b a), repeated for pads
+# wider than the axis
+PAD_MODE = {oracle.REPLICATE: "edge", oracle.ZERO: "constant", oracle.REFLECT: "symmetric"}
+BOUNDARIES = [oracle.REPLICATE, oracle.ZERO, oracle.REFLECT]
+
+
 def _brute_2d(img, h, boundary):
     """Direct 2D convolution with the outer product h x h (never separable)."""
     R = (len(h) - 1) // 2
-    mode = "edge" if boundary == oracle.REPLICATE else "constant"
+    mode = PAD_MODE[boundary]
     x = _pad(img.astype(np.float64), R, mode)
     H, W = img.shape[:2]
     K2 = np.outer(h, h)
@@ -32,7 +39,7 @@ def _brute_2d(img, h, boundary):
 
 def _brute_2d_int(img, hm, boundary):
     R = (len(hm) - 1) // 2
-    mode = "edge" if boundary == oracle.REPLICATE else "constant"
+    mode = PAD_MODE[boundary]
     x = _pad(img.astype(np.int64), R, mode)
     H, W = img.shape[:2]
     K2 = np.outer(hm, hm).astype(np.int64)
@@ -47,7 +54,7 @@ SHAPES = [(1, 1, 1), (1, 9, 1), (9, 1, 1), (7, 5, 1), (13, 11, 3), (2, 31, 2), (
 
 
 @pytest.mark.parametrize("H,W,C", SHAPES)
-@pytest.mark.parametrize("boundary", [oracle.REPLICATE, oracle.ZERO])
+@pytest.mark.parametrize("boundary", BOUNDARIES)
 @pytest.mark.parametrize("sigma,k", [(1.0, 3), (2.0, 4), (5.0, 3), (3.3, 5)])
 def test_box_f64_equals_2d_brute_force(H, W, C, boundary, sigma, k):
     b = oracle.boxes(sigma, k)
@@ -59,7 +66,7 @@ def test_box_f64_equals_2d_brute_force(H, W, C, boundary, sigma, k):
 
 
 @pytest.mark.parametrize("H,W,C", SHAPES)
-@pytest.mark.parametrize("boundary", [oracle.REPLICATE, oracle.ZERO])
+@pytest.mark.parametrize("boundary", BOUNDARIES)
 @pytest.mark.parametrize("sigma,k", [(1.0, 3), (5.0, 3), (3.3, 5)])
 def test_box_u8_equals_exact_2d_brute_force(H, W, C, boundary, sigma, k):
     b = oracle.boxes(sigma, k)
@@ -146,16 +153,31 @@ def test_u8_is_within_half_a_level_of_the_rational_result():
     assert np.max(np.abs(out8 - outf)) <= 0.5 + 1e-9
 
 
-def test_points_match_full_filter():
+@pytest.mark.parametrize("sigma,k", [(1.0, 3), (5.0, 3), (9.0, 5)])
+def test_reflect_matches_scipy_correlate1d(sigma, k):
+    """Reflect boundary against scipy's separable correlation in its
+    half-sample 'reflect' mode, with the fitted 1D step kernel along each
+    axis; the smallest shapes put boxes many times wider than the image."""
+    b = oracle.boxes(sigma, k)
+    h = oracle.kernel_1d(b["r"], b["w"])
+    for H, W in ((40, 33), (3, 50), (1, 2)):
+        img = synthimg.image(H, W, 1, "f32", seed=H + W).astype(np.float64)
+        ref = ndimage.correlate1d(ndimage.correlate1d(img, h, axis=1, mode="reflect"), h, axis=0, mode="reflect")
+        out = oracle.box_filter(img, b["r"], b["w"], oracle.REFLECT)
+        assert np.max(np.abs(out - ref)) <= 1e-11 * 255
+
+
+@pytest.mark.parametrize("boundary", BOUNDARIES)
+def test_points_match_full_filter(boundary):
     b = oracle.boxes(7.0, 4)
     img = synthimg.image(50, 70, 3, "f32", seed=6).astype(np.float64)
     img8 = synthimg.image(50, 70, 3, "u8", seed=6)
-    full = oracle.box_filter(img, b["r"], b["w"])
-    full8 = oracle.box_filter_u8(img8, b["r"], b["m"], b["G"])
+    full = oracle.box_filter(img, b["r"], b["w"], boundary)
+    full8 = oracle.box_filter_u8(img8, b["r"], b["m"], b["G"], boundary)
     rng = np.random.default_rng(0)
     ys, xs, cs = rng.integers(0, 50, 200), rng.integers(0, 70, 200), rng.integers(0, 3, 200)
-    pts = oracle.box_filter_points(img, b["r"], b["w"], ys, xs, cs)
-    pts8 = oracle.box_filter_u8_points(img8, b["r"], b["m"], b["G"], ys, xs, cs)
+    pts = oracle.box_filter_points(img, b["r"], b["w"], ys, xs, cs, boundary=boundary)
+    pts8 = oracle.box_filter_u8_points(img8, b["r"], b["m"], b["G"], ys, xs, cs, boundary=boundary)
     assert np.max(np.abs(pts - full[ys, xs, cs])) <= 1e-11
     assert np.array_equal(pts8, full8[ys, xs, cs])
 
@@ -169,6 +191,9 @@ def test_gauss_matches_scipy(sigma):
     R = int(math.ceil(6 * sigma))
     ref = ndimage.gaussian_filter(img, sigma, mode="nearest", radius=R)
     out = oracle.gauss_filter(img, sigma)
+    assert np.max(np.abs(out - ref)) <= 1e-10
+    ref = ndimage.gaussian_filter(img, sigma, mode="reflect", radius=R)
+    out = oracle.gauss_filter(img, sigma, oracle.REFLECT)
     assert np.max(np.abs(out - ref)) <= 1e-10
 
 
@@ -215,7 +240,7 @@ def test_gauss_points_match_full_filter():
     img = synthimg.image(70, 90, 3, "f32", seed=5).astype(np.float64)
     rng = np.random.default_rng(2)
     ys, xs, cs = rng.integers(0, 70, 200), rng.integers(0, 90, 200), rng.integers(0, 3, 200)
-    for boundary in (oracle.REPLICATE, oracle.ZERO):
+    for boundary in BOUNDARIES:
         full = oracle.gauss_filter(img, 3.5, boundary)
         pts = oracle.gauss_filter_points(img, 3.5, ys, xs, cs, boundary=boundary)
         assert np.max(np.abs(pts - full[ys, xs, cs])) <= 1e-9
