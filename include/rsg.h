@@ -46,13 +46,15 @@ typedef enum {
     RSG_EBUSY = -3,         /* queue full; try again later */
     RSG_ENOTFOUND = -4,     /* unknown ticket */
     RSG_EDEVICE = -5,       /* HIP runtime error */
-    RSG_EUNSUPPORTED = -6   /* valid but not supported (e.g. K > 5, REFLECT) */
+    RSG_EUNSUPPORTED = -6   /* valid but not supported (e.g. K > 5) */
 } rsg_status;
 
 typedef enum { RSG_U8 = 0, RSG_F32 = 1, RSG_F16 = 2, RSG_BF16 = 3 } rsg_dtype;
 
-/* REPLICATE clamps indices to the image; ZERO treats samples outside as 0.
- * REFLECT is reserved and returns RSG_EUNSUPPORTED. */
+/* Boundary extension of each axis (the paper names none).  REPLICATE clamps
+ * indices to the image; ZERO treats samples outside as 0; REFLECT is the
+ * half-sample symmetric extension (... c b a | a b c d | d c b ...), repeated
+ * with period 2n, so boxes wider than the image are defined in every mode. */
 typedef enum { RSG_REPLICATE = 0, RSG_ZERO = 1, RSG_REFLECT = 2 } rsg_boundary;
 
 #define RSG_MAX_K 5
@@ -92,15 +94,18 @@ typedef struct {
  * Errors: RSG_EINVAL (sigma, K, out == NULL), RSG_EUNSUPPORTED (K > 5). */
 int rsg_fit_boxes(double sigma, int K, rsg_boxes* out);
 
-/* Filter one image: rows by the K boxes, then columns (Sections 3.3-3.4), in
- * one fused kernel launch on `stream`.  uint8 is computed in exact integers
+/* Filter one image: rows by the K boxes, then columns (Sections 3.3-3.4), on
+ * `stream`: one fused kernel launch, or for wide boxes two launches of a row
+ * filter with a transposed store and a stream-ordered intermediate of
+ * H*W*C four-byte words (hipMallocAsync / hipFreeAsync on `stream`).  uint8 is computed in exact integers
  * (uint32 running sums, one rounding at the end: round half up of U / G^2);
  * FP32 / FP16 / BF16 load as FP32 and accumulate in FP32; FP16 / BF16
  * results are rounded to nearest even.  Row stride = W*C elements.
  * Errors: RSG_EINVAL (NULL pointers, H or W < 1, C not in 1..4, bad dtype,
- * sigma <= 0 or not finite, K not in 1..5), RSG_EUNSUPPORTED (REFLECT,
- * uint8 with no admissible integer scale, box wider than the kernel limits),
- * RSG_EDEVICE (launch failure). */
+ * sigma <= 0 or not finite, K not in 1..5, bad boundary), RSG_EUNSUPPORTED
+ * (uint8 with no admissible integer scale, box wider than the kernel limits),
+ * RSG_ENOMEM (no device memory for the intermediate), RSG_EDEVICE (launch
+ * failure). */
 int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt,
                      double sigma, int K, rsg_boundary b, void* stream);
 

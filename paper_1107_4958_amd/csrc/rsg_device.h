@@ -7,8 +7,8 @@
 //   row pass (Section 3.3, Eq. alg1 / indep, along x): the wave splits into
 //     G = 64 / SEG segments of SEG lanes; segment j takes input row
 //     (group start + j), lane q of the segment holds NPL consecutive samples
-//     of the row span [s0 - (R+1)C, s0 + 64 + RC) (border samples replicated
-//     or zero).  The running sum I of each row is a serial scan inside the
+//     of the row span [s0 - (R+1)C, s0 + 64 + RC) (border samples replicated,
+//     reflected or zero).  The running sum I of each row is a serial scan inside the
 //     lane plus a DPP scan of the lane totals across the segment; the G rows
 //     of running sums go to LDS.  Then every lane (now: a column) takes
 //     T(s) = sum_k w_k (I(s + r_k C) - I(s - (r_k+1) C)) for each row.
@@ -126,6 +126,23 @@ struct TrBF16 {
 };
 
 __device__ __forceinline__ int floor_div(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+// Boundary extension of index i on an axis of n samples: the index whose
+// sample stands at i, or -1 for a zero sample.  Replicate clamps; reflect is
+// the half-sample symmetric extension (f(-1) = f(0), f(n) = f(n - 1)),
+// periodic with period 2n so that boxes wider than the axis are defined.
+__device__ __forceinline__ int ext_index(int i, int n, int boundary)
+{
+    if (i >= 0 && i < n) return i;
+    if (boundary == RSG_REPLICATE) return i < 0 ? 0 : n - 1;
+    if (boundary == RSG_REFLECT) {
+        const int p = 2 * n;
+        int m = i % p;
+        m += (m < 0) ? p : 0;
+        return m < n ? m : p - 1 - m;
+    }
+    return -1;
+}
 
 // Raw chunk of NPL samples held in 32-bit words until it is consumed.
 template <class Tr, int NPL>
@@ -294,7 +311,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     const int H = ip.H;
     const int W = ip.W;
     const int WC = W * C;
-    const bool replicate = (ip.boundary == RSG_REPLICATE);
+    const int boundary = ip.boundary;
 
     Acc* P = reinterpret_cast<Acc*>(lds);      // 2 tiles of G rows x PW running sums (pitch PP)
     Acc* ring = P + 2 * G * PP;                // (L + G) rows x 64 column sums (pitch RP)
@@ -326,16 +343,18 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 #pragma unroll
         for (int i = 0; i < NPL; ++i) {
             const int x = x0 + i / C;
-            const int xc = x < 0 ? 0 : (x >= W ? W - 1 : x);
-            eoff[i] = (replicate || (x >= 0 && x < W)) ? (xc * C + i % C) * es : -1;   // -1: zero sample
+            const int xe = ext_index(x, W, boundary);
+            eoff[i] = (xe >= 0) ? (xe * C + i % C) * es : -1;    // -1: zero sample
         }
     }
     const int sstride32 = int(sstride);
     auto load = [&](Chunk<Tr, NPL>& ch, int g) {
         const int y = tg.ybase + g * G + jrow;
-        const int yc = y < 0 ? 0 : (y >= H ? H - 1 : y);
-        const bool zero_row = !replicate && yc != y;      // ZERO boundary: rows outside read as 0
-        const int rowoff = (yc - y_lo) * sstride32;       // rows past the task end: re-read, unused
+        // Every row a task needs maps into [y_lo, H - 1]; rows past the task
+        // end (re-read, unused) may not, and then read as 0 or any row.
+        const int ye = ext_index(y, H, boundary);
+        const bool zero_row = ye < 0;                     // ZERO boundary: rows outside read as 0
+        const int rowoff = (zero_row ? 0 : ye - y_lo) * sstride32;
         if constexpr (EDGE) {
             int vo[NPL];
 #pragma unroll
@@ -618,7 +637,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
     const int H = ip.H;
     const int W = ip.W;
     const int WC = W * C;
-    const bool replicate = (ip.boundary == RSG_REPLICATE);
+    const int boundary = ip.boundary;
     static_assert(PW <= PP, "tile pitch");
 
     // LDS: [row tile G x PP][queue 2 x G x 64][column offsets 64][ring (L + G) x 64]
@@ -655,16 +674,16 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
                 const int x = x0 + i / C;
-                const int xc = x < 0 ? 0 : (x >= W ? W - 1 : x);
-                eoff[i] = (replicate || (x >= 0 && x < W)) ? (xc * C + i % C) * es : -1;
+                const int xe = ext_index(x, W, boundary);
+                eoff[i] = (xe >= 0) ? (xe * C + i % C) * es : -1;
             }
         }
         const int sstride32 = int(sstride);
         auto load = [&](Chunk<Tr, NPL>& ch, int g) {
             const int y = tg.ybase + g * G + jrow;
-            const int yc = y < 0 ? 0 : (y >= H ? H - 1 : y);
-            const bool zero_row = !replicate && yc != y;
-            const int rowoff = (yc - y_lo) * sstride32;
+            const int ye = ext_index(y, H, boundary);
+            const bool zero_row = ye < 0;
+            const int rowoff = (zero_row ? 0 : ye - y_lo) * sstride32;
             if constexpr (EDGE) {
                 int vo[NPL];
 #pragma unroll

@@ -119,8 +119,8 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     if (d.H < 1 || d.W < 1) return set_error(RSG_EINVAL, "H and W must be >= 1 (got %d x %d)", d.H, d.W);
     if (d.C < 1 || d.C > 4) return set_error(RSG_EINVAL, "C must be in 1..4 (got %d)", d.C);
     if (d.dt < RSG_U8 || d.dt > RSG_BF16) return set_error(RSG_EINVAL, "bad dtype %d", int(d.dt));
-    if (d.b == RSG_REFLECT) return set_error(RSG_EUNSUPPORTED, "REFLECT boundary is not supported");
-    if (d.b != RSG_REPLICATE && d.b != RSG_ZERO) return set_error(RSG_EINVAL, "bad boundary %d", int(d.b));
+    if (d.b != RSG_REPLICATE && d.b != RSG_ZERO && d.b != RSG_REFLECT)
+        return set_error(RSG_EINVAL, "bad boundary %d", int(d.b));
     const int64_t WC = int64_t(d.W) * d.C;
     if (WC > (int64_t(1) << 30) || d.H > (1 << 30)) return set_error(RSG_EUNSUPPORTED, "image too large");
     const int64_t ss = d.src_stride ? d.src_stride : WC;

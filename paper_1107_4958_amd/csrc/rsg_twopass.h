@@ -63,14 +63,16 @@ __device__ __forceinline__ void store_pass_out(void* dst, int64_t idx, uint32_t 
 }
 
 // Boundary-extended position inside a row of `len` samples whose channels
-// repeat every C samples: -1 means a zero sample.
+// repeat every C samples (the pixel index is extended, the channel kept):
+// -1 means a zero sample.
 template <int C>
-__device__ __forceinline__ int pass_clamp(int pos, int len, bool replicate)
+__device__ __forceinline__ int pass_clamp(int pos, int len, int boundary)
 {
     if (pos >= 0 && pos < len) return pos;
-    if (!replicate) return -1;
-    const int c = ((pos % C) + C) % C;
-    return pos < 0 ? c : len - C + c;
+    const int x = floor_div(pos, C);
+    const int c = pos - x * C;
+    const int xe = ext_index(x, len / C, boundary);
+    return xe < 0 ? -1 : xe * C + c;
 }
 
 template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
@@ -88,7 +90,7 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
     const int R = p.R;
     const int HW = (2 * R + 1) * C;                // window head: running sums kept from the previous chunk
     const int len = p.len;
-    const bool replicate = (p.boundary == RSG_REPLICATE);
+    const int boundary = p.boundary;
 
     // per-wave window (the head starts so that the new part is 16-byte aligned)
     Acc* win = reinterpret_cast<Acc*>(lds) + wave * p.win_pitch + p.win_shift;
@@ -118,7 +120,7 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
     if constexpr (!kInt) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int q = pass_clamp<C>(c, len, true);
+            const int q = pass_clamp<C>(c, len, RSG_REPLICATE);
             off[c] = Tr_load_one<TrIn>(rs, q * es);
         }
 #pragma unroll
@@ -142,7 +144,7 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
             int eo[NPL];
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-                const int q = pass_clamp<C>(a + i, len, replicate);
+                const int q = pass_clamp<C>(a + i, len, boundary);
                 eo[i] = q < 0 ? kDropOffset : q * es;
             }
             load_chunk_elem<TrIn, NPL>(ch, rs, eo, 0);

@@ -91,7 +91,7 @@ def test_gauss_filter_rejects_bad_arguments_before_any_device_call():
         ((A, B, 8, 8, 1, rsg.RSG_F32, 0.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
         ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 0, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
         ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 6, rsg.RSG_REPLICATE), rsg.RSG_EUNSUPPORTED),
-        ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REFLECT), rsg.RSG_EUNSUPPORTED),
+        ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 3, 3), rsg.RSG_EINVAL),
         ((A, B, 8, 8, 1, rsg.RSG_F32, 2.0, 3, 9), rsg.RSG_EINVAL),
         ((A, ctypes.c_void_p(0x100000 + 64), 8, 8, 1, rsg.RSG_F32, 2.0, 3, rsg.RSG_REPLICATE), rsg.RSG_EINVAL),
     ]

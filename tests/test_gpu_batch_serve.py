@@ -78,9 +78,10 @@ def test_batch_mixed_identical_to_alone():
             _spot_check(it["img"], got, it["dtype"], it["sigma"], it["K"])
 
 
-def test_batch_zero_boundary_and_repeat():
-    """ZERO boundary in a batch; a second launch reusing the workspace gives
-    the same bits."""
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_batch_boundary_and_repeat(boundary):
+    """ZERO and REFLECT boundaries in a batch; a second launch reusing the
+    workspace gives the same bits."""
     import torch
     rsg = _rsg()
     items = _mixed_images()[:6]
@@ -89,15 +90,15 @@ def test_batch_zero_boundary_and_repeat():
     d2 = [torch.empty_like(s) for s in srcs]
     sg = [it["sigma"] for it in items]
     Ks = [it["K"] for it in items]
-    ws = rsg.filter_batch_tensors(srcs, d1, sg, Ks, boundary=rsg.RSG_ZERO)
-    rsg.filter_batch_tensors(srcs, d2, sg, Ks, boundary=rsg.RSG_ZERO, workspace=ws)
+    ws = rsg.filter_batch_tensors(srcs, d1, sg, Ks, boundary=boundary)
+    rsg.filter_batch_tensors(srcs, d2, sg, Ks, boundary=boundary, workspace=ws)
     torch.cuda.synchronize()
     for it, s, a, b in zip(items, srcs, d1, d2):
-        alone = from_device(_alone(s, it["sigma"], it["K"], rsg.RSG_ZERO), it["dtype"])
+        alone = from_device(_alone(s, it["sigma"], it["K"], boundary), it["dtype"])
         assert np.array_equal(from_device(a, it["dtype"]).view(np.uint8), alone.view(np.uint8))
         assert np.array_equal(from_device(b, it["dtype"]).view(np.uint8), alone.view(np.uint8))
-        if it["dtype"] == "u8":
-            _spot_check(it["img"], from_device(a, "u8"), "u8", it["sigma"], it["K"], rsg.RSG_ZERO)
+        if it["dtype"] in ("u8", "f32"):
+            _spot_check(it["img"], from_device(a, it["dtype"]), it["dtype"], it["sigma"], it["K"], boundary)
 
 
 def test_batch_256_three_channel_u8():

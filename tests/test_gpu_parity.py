@@ -46,7 +46,7 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("dtype", ["f32", "u8"])
-@pytest.mark.parametrize("boundary", [oracle.REPLICATE, oracle.ZERO])
+@pytest.mark.parametrize("boundary", [oracle.REPLICATE, oracle.ZERO, oracle.REFLECT])
 @pytest.mark.parametrize("H,W,C,sigma,K", SHAPES)
 def test_parity_shapes(dtype, boundary, H, W, C, sigma, K):
     img = synthimg.image(H, W, C, dtype, seed=H * 31 + W)
@@ -103,8 +103,8 @@ def _sample_points(H, W, C, n, seed):
     ys = list(rng.integers(0, H, n))
     xs = list(rng.integers(0, W, n))
     # corners and edges
-    for y in (0, 1, H // 2, H - 2, H - 1):
-        for x in (0, 1, W // 2, W - 2, W - 1):
+    for y in (0, 1, 7, 23, H // 2, H - 24, H - 8, H - 2, H - 1):
+        for x in (0, 1, 7, 23, W // 2, W - 24, W - 8, W - 2, W - 1):
             ys.append(max(0, y))
             xs.append(max(0, x))
     ys = np.array(ys) % H
@@ -113,20 +113,21 @@ def _sample_points(H, W, C, n, seed):
     return ys, xs, cs
 
 
-def _sampled_check(H, W, C, dtype, sigma, K, npts=1500, seed=0):
+def _sampled_check(H, W, C, dtype, sigma, K, npts=1500, seed=0, boundary=oracle.REPLICATE):
     b = oracle.boxes(sigma, K)
     img = synthimg.image(H, W, C, dtype, seed=seed)
-    out = gpu_filter(img, dtype, sigma, K)
+    out = gpu_filter(img, dtype, sigma, K, boundary)
     if out.ndim == 2:
         out = out[..., None]
     img3 = img if img.ndim == 3 else img[..., None]
     ys, xs, cs = _sample_points(H, W, C, npts, seed + 1)
     if dtype == "u8":
-        ref = oracle.box_filter_u8_points(img3, b["r"], b["m"], b["G"], ys, xs, cs)
+        ref = oracle.box_filter_u8_points(img3, b["r"], b["m"], b["G"], ys, xs, cs, boundary=boundary)
         got = out[ys, xs, cs]
         assert np.array_equal(got, ref), "uint8 sampled mismatch"
         return
-    ref = oracle.box_filter_points(decode(img3, dtype), b["r"], b["w32"].astype(np.float64), ys, xs, cs)
+    ref = oracle.box_filter_points(decode(img3, dtype), b["r"], b["w32"].astype(np.float64), ys, xs, cs,
+                                   boundary=boundary)
     got = out[ys, xs, cs]
     if dtype == "f32":
         den = float(np.max(np.abs(decode(img3, dtype))))   # max|ref| <= max|input| (unit DC gain)
@@ -140,6 +141,12 @@ def _sampled_check(H, W, C, dtype, sigma, K, npts=1500, seed=0):
 @pytest.mark.parametrize("K", [3, 4, 5])
 def test_at_scale_4096(dtype, sigma, K):
     _sampled_check(4096, 4096, 1, dtype, sigma, K, npts=800, seed=2)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+@pytest.mark.parametrize("sigma", [8.0, 32.0])
+def test_at_scale_4096_reflect(dtype, sigma):
+    _sampled_check(4096, 4096, 1, dtype, sigma, 3, npts=800, seed=3, boundary=oracle.REFLECT)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "u8", "f16", "bf16"])
@@ -168,6 +175,9 @@ TWO_PASS_SHAPES = [
     (97, 250, 2, 4.0, 4, 0), (61, 211, 3, 6.0, 5, 1), (200, 333, 1, 8.0, 3, 0), (130, 77, 3, 20.0, 4, 0),
     (257, 259, 1, 32.0, 5, 1), (700, 300, 1, 12.0, 5, 0), (1000, 129, 1, 40.0, 3, 0), (33, 2000, 4, 5.0, 3, 1),
     (520, 1030, 1, 64.0, 5, 0), (64, 64, 1, 1.0, 1, 0),
+    # reflect: boxes many times wider than the axis, and every channel count
+    (5, 3, 1, 8.0, 5, 2), (300, 1, 1, 3.0, 4, 2), (61, 211, 3, 6.0, 5, 2), (257, 259, 1, 32.0, 5, 2),
+    (33, 2000, 4, 5.0, 3, 2), (97, 250, 2, 4.0, 4, 2),
 ]
 
 
@@ -208,7 +218,8 @@ def test_paths_agree(dtype):
 
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 @pytest.mark.parametrize("H,W,C,sigma,K,boundary", [(200, 333, 1, 8.0, 3, 0), (97, 250, 2, 4.0, 4, 1),
-                                                    (61, 211, 3, 6.0, 5, 0), (33, 520, 1, 0.5, 5, 1)])
+                                                    (61, 211, 3, 6.0, 5, 0), (33, 520, 1, 0.5, 5, 1),
+                                                    (70, 90, 4, 2.5, 3, 2), (130, 77, 3, 20.0, 4, 2)])
 def test_one_wave_fused_form(dtype, H, W, C, sigma, K, boundary):
     """The fused kernel with one wave per task (the form batched launches
     run) forced for single images."""

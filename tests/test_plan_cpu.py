@@ -122,3 +122,15 @@ def test_wide_boxes_take_the_two_pass_path():
     R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
     _run_planner_code("assert rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))[0] == 4096\n",
                       "1 1 %d %d 0 %d -1\n" % (R, R, 1 << 40))
+
+
+def test_plan_does_not_depend_on_the_boundary():
+    """Every boundary mode plans the same tile (the extension only changes
+    which samples the border loads read)."""
+    for H, W, C, sigma in ((4096, 4096, 1, 8.0), (37, 523, 3, 7.5), (1, 1, 1, 2.0), (96, 96, 4, 40.0)):
+        shapes = []
+        for b in (rsg.RSG_REPLICATE, rsg.RSG_ZERO, rsg.RSG_REFLECT):
+            d = _desc(H, W, C, sigma=sigma)
+            d.b = b
+            shapes.append(rsg.rsg_plan_shape(d))
+        assert shapes[0] == shapes[1] == shapes[2], (H, W, C, shapes)
