@@ -158,6 +158,37 @@ def quant_u8(r, w):
     return m, int(G[0]), int(s[0])
 
 
+def direct_half_samples(sigma: float, k: int) -> int:
+    """Half samples M of the direct fit at sigma: the Section 4.2 support
+    [-pi sigma, pi sigma) holds ceil(pi sigma) samples t = 0..M-1 on the
+    positive half (100 at sigma0), and at least k so that k distinct
+    half-widths exist."""
+    return max(int(math.ceil(math.pi * sigma - 1e-9)), int(k))
+
+
+def boxes_direct(sigma: float, k: int) -> dict:
+    """Direct fit at sigma (a reading: the paper fits once at sigma0 and
+    rescales, Section 4.2): the same exhaustive search of the quadratic form
+    (Section 4.1, Eq. mahal) run on the Gaussian of s.d. sigma itself, over M
+    half samples with Phi on period 2M.  The half-widths are the partition
+    (r = p), the slice weights w_i = c_i - c_{i+1} are normalised to unit DC
+    gain, and the FP32 and uint8 forms follow as for the rescaled fit."""
+    M = direct_half_samples(sigma, k)
+    p, c, err = fit(k, nh=M, sigma0=float(sigma), N=2 * M)
+    p = np.asarray(p, dtype=np.int32)
+    c = np.asarray(c, dtype=np.float64)
+    slices = c - np.append(c[1:], 0.0)
+    r = p.copy()
+    w = slices / float(np.sum(slices * (2.0 * r + 1.0)))
+    w32 = w.astype(np.float32)
+    try:
+        m, G, s = quant_u8(r, w)
+    except ValueError:
+        m, G, s = None, None, None
+    return dict(sigma=float(sigma), k=int(k), p=p, c=c, fit_err=err, r=r, w=w, w32=w32,
+                m=m, G=G, s=s, M=M)
+
+
 def boxes(sigma: float, k: int, *, use_qf=True) -> dict:
     """Everything the filter needs for one (sigma, k): the oracle's own fit."""
     p, c, err = fit(k, use_qf=use_qf)

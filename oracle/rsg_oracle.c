@@ -49,6 +49,9 @@
  *     d c b ...) repeated with period 2n for boxes wider than the axis;
  *     channels interleaved and filtered independently;
  *   - uint8 output: round half up of the exact rational U / G^2.
+ * The direct fit at a target sigma (oracle/__init__.py, boxes_direct) runs
+ * orc_fit on the Gaussian of that sigma with M = max(ceil(pi sigma), K) half
+ * samples and Phi on period 2M, and takes r = p.
  */
 #include <math.h>
 #include <stdint.h>

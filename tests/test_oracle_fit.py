@@ -218,3 +218,77 @@ def test_u8_integer_weights_bounds(sigma, k):
     hq = oracle.kernel_1d(r, m.astype(np.float64) / G)
     h = oracle.kernel_1d(r, b["w"])
     assert np.max(np.abs(hq - h)) <= k * 0.5 / G + 1e-15
+
+
+# --------------------------------------------------------------------------
+# Direct fit at the target sigma (the fit of Section 4 run at sigma itself)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("sigma", [0.5, 1.0, 2.2, 3.5])
+def test_direct_fit_matches_brute_force(k, sigma):
+    """Every partition of the M = ceil(pi sigma) half samples enumerated with
+    dense matrices (Phi on period 2M from numpy's inverse FFT)."""
+    import itertools
+    M = oracle.direct_half_samples(sigma, k)
+    best = None
+    for p in itertools.combinations(range(M), k):
+        t, g, A = _dense_problem(M, sigma, True, N=2 * M)
+        c, e = _dense_eval_problem(list(p), t, g, A)
+        if best is None or e < best[1] - 1e-12:
+            best = (p, e, c)
+    b = oracle.boxes_direct(sigma, k)
+    assert tuple(b["p"]) == tuple(best[0])
+    assert abs(b["fit_err"] - best[1]) < 1e-10
+    assert np.allclose(b["c"], best[2], rtol=1e-9, atol=1e-12)
+
+
+def _dense_eval_problem(p, t, g, A):
+    at = np.abs(t)
+    B = np.zeros((len(t), len(p)))
+    lo = -1
+    for i, pi in enumerate(p):
+        B[(at > lo) & (at <= pi), i] = 1.0
+        lo = pi
+    c = np.linalg.solve(B.T @ A @ B, B.T @ A @ g)
+    e = g - B @ c
+    return c, float(e @ A @ e)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_direct_fit_at_sigma0_is_table2(k):
+    """At sigma = sigma0 = 100/pi the direct problem is the paper's own
+    (100 half samples, period 200): Table 2's partition as the half-widths,
+    and the 1D kernel on segment i proportional to Table 2's printed c_i
+    (printed to 4 decimals).  The rescaled fit differs here: Eq. scale2's
+    factor p_i / (2 r_i + 1) is not the identity at sigma0."""
+    b = oracle.boxes_direct(oracle.SIGMA0, k)
+    assert b["M"] == 100
+    assert list(b["p"]) == GOLD["table2"][str(k)]["p"]
+    assert list(b["r"]) == GOLD["table2"][str(k)]["p"]
+    h = oracle.kernel_1d(b["r"], b["w"])
+    R = int(b["r"][-1])
+    levels = np.array([h[R + pi] for pi in b["p"]])          # kernel level on each segment
+    c_printed = np.array(GOLD["table2"][str(k)]["c"])
+    assert np.allclose(levels / levels[0], c_printed / c_printed[0], rtol=0, atol=6e-4)
+
+
+@pytest.mark.parametrize("sigma,k", [(0.5, 5), (0.8, 3), (1.0, 4), (1.5, 5), (2.0, 3)])
+def test_direct_fit_removes_the_small_sigma_degeneracy(sigma, k):
+    """Rescaling the sigma0 fit floors several half-widths to the same small
+    value at small sigma; the direct fit has distinct half-widths and a 1D
+    kernel closer (l2) to the normalised sampled Gaussian."""
+    t = np.arange(-40, 41)
+    g = np.exp(-t.astype(np.float64) ** 2 / (2 * sigma ** 2))
+    g /= g.sum()
+
+    def l2(b):
+        h = oracle.kernel_1d(b["r"], b["w"])
+        R = (len(h) - 1) // 2
+        hh = np.zeros_like(g)
+        hh[40 - R:40 + R + 1] = h
+        return float(np.linalg.norm(hh - g))
+
+    d, s = oracle.boxes_direct(sigma, k), oracle.boxes(sigma, k)
+    assert len(set(d["r"].tolist())) == k
+    assert abs(float(np.sum(d["w"] * (2 * d["r"] + 1))) - 1.0) < 1e-14
+    assert l2(d) < l2(s)
