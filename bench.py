@@ -196,6 +196,34 @@ def plain_workload(steps):
             "note": "2 MiB: resident in the last-level cache, no roofline"}
 
 
+def fit_study():
+    """The fit methods compared on the method's own accuracy (the analogue of
+    the paper's parameter comparison): a 1024 x 1024 FP32 1/f image filtered
+    on the device with the boxes of each method, PSNR and NRMS against the
+    sampled Gaussian (FP64 oracle), for sigma in {1, 2, 4, 8, 16} and K in
+    {3, 4, 5}.  Methods: the paper's rescaled quadratic-form fit, the
+    rescaled l2 fit, and the direct quadratic-form fit at sigma."""
+    import oracle
+    import paper_1107_4958_amd as rsg
+    import synthimg
+    img = synthimg.image(1024, 1024, 1, "f32", 21)
+    x = img.astype(np.float64)
+    src = to_dev(img, "f32")
+    methods = (("scaled_qf", rsg.RSG_FIT_SCALED), ("scaled_l2", rsg.RSG_FIT_SCALED_L2), ("direct_qf", rsg.RSG_FIT_DIRECT))
+    out = []
+    for sigma in (1.0, 2.0, 4.0, 8.0, 16.0):
+        g = oracle.gauss_filter(x, sigma).reshape(img.shape)
+        for K in (3, 4, 5):
+            row = {"sigma": sigma, "K": K}
+            for name, m in methods:
+                b = rsg.rsg_fit_boxes_ex(sigma, K, m)
+                o = from_dev(rsg.filter_tensor(src, sigma, K, boxes=b), "f32").astype(np.float64)
+                row[name] = {"r": [int(v) for v in b.r[:K]], "psnr_db": round(oracle.psnr(o, g), 2),
+                             "nrms": float("%.4g" % oracle.nrms(o, g))}
+            out.append(row)
+    return out
+
+
 def sigma_k_grid(imgs, steps):
     """Gpixel/s and HBM fraction at 4096^2 for sigma in {2, 8, 32}, K in {3, 4, 5}."""
     out = []
@@ -467,6 +495,8 @@ def main():
         result["sigma_K_grid_4096"] = sigma_k_grid(imgs, max(20, args.steps // 4))
         print("bench: plain 512^2", file=sys.stderr, flush=True)
         result["plain_512"] = plain_workload(200)
+        print("bench: fit methods", file=sys.stderr, flush=True)
+        result["fit_study_1024"] = fit_study()
         print("bench: batch", file=sys.stderr, flush=True)
         result["batch"] = batch_workload(5, gpx if args.dtype == "f32" else None)
         print("bench: precision", file=sys.stderr, flush=True)

@@ -90,9 +90,29 @@ typedef struct {
 /* Fit and rescale the boxes for (sigma, K) on the host, in FP64 (the only
  * FP64 computation of the library).  The sigma0 search is exhaustive over all
  * C(100, K) partitions and is cached per K for the life of the process
- * (thread-safe).  sigma must be finite and > 0; K in 1..5.
+ * (thread-safe).  sigma must be finite and > 0; K in 1..5.  This is the fit
+ * every entry point uses unless the caller passes boxes of its own.
  * Errors: RSG_EINVAL (sigma, K, out == NULL), RSG_EUNSUPPORTED (K > 5). */
 int rsg_fit_boxes(double sigma, int K, rsg_boxes* out);
+
+/* Fit methods:
+ *   RSG_FIT_SCALED     the paper's: the quadratic-form fit at sigma0 rescaled
+ *                      to sigma (Section 4.2), as rsg_fit_boxes;
+ *   RSG_FIT_SCALED_L2  the same with the l2 error (A = I), the error measure
+ *                      the paper compares its quadratic form against;
+ *   RSG_FIT_DIRECT     the Section 4 search run at sigma itself: the Gaussian
+ *                      of s.d. sigma on M = max(ceil(pi sigma), K) half
+ *                      samples, Phi on period 2M, r = p (the partition), w
+ *                      the slices c_k - c_{k+1} normalised to unit DC gain
+ *                      (p, c, fit_err describe this fit).  For sigma <=
+ *                      100/pi, where rescaling floors half-widths together;
+ *                      cached per (K, sigma), bounded. */
+typedef enum { RSG_FIT_SCALED = 0, RSG_FIT_SCALED_L2 = 1, RSG_FIT_DIRECT = 2 } rsg_fit_method;
+
+/* Boxes for (sigma, K) by one of the fit methods above.
+ * Errors: as rsg_fit_boxes; RSG_EINVAL (bad method); RSG_EUNSUPPORTED
+ * (RSG_FIT_DIRECT with sigma > 100/pi). */
+int rsg_fit_boxes_ex(double sigma, int K, rsg_fit_method method, rsg_boxes* out);
 
 /* Filter one image: rows by the K boxes, then columns (Sections 3.3-3.4), on
  * `stream`: one fused kernel launch, or for wide boxes two launches of a row
@@ -109,6 +129,15 @@ int rsg_fit_boxes(double sigma, int K, rsg_boxes* out);
 int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt,
                      double sigma, int K, rsg_boundary b, void* stream);
 
+/* rsg_gauss_filter with boxes the caller supplies (any fit method, or boxes
+ * of its own): K in 1..5, half-widths r_k in [0, 2^26], FP32 weights w32
+ * finite; for uint8 the integer form must be present (u8_ok) and consistent:
+ * G = sum m_k (2 r_k + 1) < 2^24 and 255 G (2 r_max + 1) < 2^32.  Only K, r,
+ * w32, m, G and u8_ok are read, during the call.
+ * Errors: as rsg_gauss_filter; RSG_EINVAL (boxes NULL or inconsistent). */
+int rsg_box_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt,
+                   const rsg_boxes* boxes, rsg_boundary b, void* stream);
+
 /* One image of a batch; strides in elements (0 means W*C). */
 typedef struct {
     const void* src;
@@ -119,6 +148,7 @@ typedef struct {
     double sigma;
     int32_t K;
     rsg_boundary b;
+    const rsg_boxes* boxes;   /* NULL: rsg_fit_boxes(sigma, K); else these boxes (read during the call) */
 } rsg_image_desc;
 
 /* Bytes of device workspace rsg_filter_batch needs for these n images.

@@ -36,6 +36,7 @@ RSG_EUNSUPPORTED = -6
 
 RSG_U8, RSG_F32, RSG_F16, RSG_BF16 = 0, 1, 2, 3
 RSG_REPLICATE, RSG_ZERO, RSG_REFLECT = 0, 1, 2
+RSG_FIT_SCALED, RSG_FIT_SCALED_L2, RSG_FIT_DIRECT = 0, 1, 2
 RSG_MAX_K = 5
 
 DTYPE_NAMES = {"u8": RSG_U8, "f32": RSG_F32, "f16": RSG_F16, "bf16": RSG_BF16}
@@ -77,6 +78,7 @@ class rsg_image_desc(ctypes.Structure):
         ("sigma", ctypes.c_double),
         ("K", ctypes.c_int32),
         ("b", ctypes.c_int),
+        ("boxes", ctypes.c_void_p),          # const rsg_boxes* or NULL
     ]
 
 
@@ -105,7 +107,7 @@ class rsg_req_stats(ctypes.Structure):
 
 SYMBOLS = ("rsg_fit_boxes", "rsg_gauss_filter", "rsg_filter_batch_workspace", "rsg_filter_batch",
            "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_plan_shape",
-           "rsg_tune_override", "rsg_tune_path", "rsg_last_error")
+           "rsg_tune_override", "rsg_tune_path", "rsg_fit_boxes_ex", "rsg_box_filter", "rsg_last_error")
 
 
 def _load():
@@ -126,6 +128,8 @@ def _load():
     V, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     lib.rsg_fit_boxes.argtypes = [D, I, ctypes.POINTER(rsg_boxes)]
     lib.rsg_gauss_filter.argtypes = [V, V, I, I, I, I, D, I, I, V]
+    lib.rsg_fit_boxes_ex.argtypes = [D, I, I, ctypes.POINTER(rsg_boxes)]
+    lib.rsg_box_filter.argtypes = [V, V, I, I, I, I, ctypes.POINTER(rsg_boxes), I, V]
     lib.rsg_filter_batch_workspace.argtypes = [ctypes.POINTER(rsg_image_desc), I, ctypes.POINTER(S)]
     lib.rsg_filter_batch.argtypes = [ctypes.POINTER(rsg_image_desc), I, V, S, V]
     lib.rsg_server_create.argtypes = [ctypes.POINTER(rsg_server_config), ctypes.POINTER(V)]
@@ -169,10 +173,22 @@ def rsg_fit_boxes(sigma: float, K: int) -> rsg_boxes:
     return out
 
 
+def rsg_fit_boxes_ex(sigma: float, K: int, method: int) -> rsg_boxes:
+    out = rsg_boxes()
+    _check(_lib.rsg_fit_boxes_ex(float(sigma), int(K), int(method), ctypes.byref(out)))
+    return out
+
+
 def rsg_gauss_filter(d_src: int, d_dst: int, H: int, W: int, C: int, dt: int, sigma: float, K: int,
                      boundary: int = RSG_REPLICATE, stream: int = 0) -> None:
     _check(_lib.rsg_gauss_filter(ctypes.c_void_p(d_src), ctypes.c_void_p(d_dst), H, W, C, dt,
                                  float(sigma), K, boundary, ctypes.c_void_p(stream)))
+
+
+def rsg_box_filter(d_src: int, d_dst: int, H: int, W: int, C: int, dt: int, boxes: rsg_boxes,
+                   boundary: int = RSG_REPLICATE, stream: int = 0) -> None:
+    _check(_lib.rsg_box_filter(ctypes.c_void_p(d_src), ctypes.c_void_p(d_dst), H, W, C, dt, ctypes.byref(boxes),
+                               boundary, ctypes.c_void_p(stream)))
 
 
 def _desc_array(descs):
@@ -261,20 +277,26 @@ def _stream_handle(t, stream):
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
-def filter_tensor(src, sigma: float, K: int, boundary: int = RSG_REPLICATE, out=None, stream=None):
-    """Filter a contiguous H x W (x C) device tensor; returns `out`."""
+def filter_tensor(src, sigma: float, K: int, boundary: int = RSG_REPLICATE, out=None, stream=None, boxes=None):
+    """Filter a contiguous H x W (x C) device tensor; returns `out`.  With
+    `boxes` (an rsg_boxes, e.g. from rsg_fit_boxes_ex) those boxes are used
+    and sigma, K are ignored."""
     import torch
     if not src.is_cuda or not src.is_contiguous():
         raise ValueError("src must be a contiguous device tensor")
     if out is None:
         out = torch.empty_like(src)
     H, W, C = _hwc(src)
-    rsg_gauss_filter(src.data_ptr(), out.data_ptr(), H, W, C, tensor_dtype_code(src), sigma, K, boundary,
-                     _stream_handle(src, stream))
+    if boxes is not None:
+        rsg_box_filter(src.data_ptr(), out.data_ptr(), H, W, C, tensor_dtype_code(src), boxes, boundary,
+                       _stream_handle(src, stream))
+    else:
+        rsg_gauss_filter(src.data_ptr(), out.data_ptr(), H, W, C, tensor_dtype_code(src), sigma, K, boundary,
+                         _stream_handle(src, stream))
     return out
 
 
-def make_desc(src, dst, sigma: float, K: int, boundary: int = RSG_REPLICATE) -> rsg_image_desc:
+def make_desc(src, dst, sigma: float, K: int, boundary: int = RSG_REPLICATE, boxes=None) -> rsg_image_desc:
     H, W, C = _hwc(src)
     d = rsg_image_desc()
     d.src = src.data_ptr()
@@ -286,6 +308,9 @@ def make_desc(src, dst, sigma: float, K: int, boundary: int = RSG_REPLICATE) -> 
     d.sigma = float(sigma)
     d.K = int(K)
     d.b = boundary
+    if boxes is not None:
+        d.boxes = ctypes.addressof(boxes)
+        d._boxes_ref = boxes                 # keeps the struct alive with the descriptor
     return d
 
 

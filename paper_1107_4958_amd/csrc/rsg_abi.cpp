@@ -91,7 +91,12 @@ int rsg_tune_override(int32_t seg_height)
 
 int rsg_fit_boxes(double sigma, int K, rsg_boxes* out)
 {
-    return rsg::make_boxes(sigma, K, true, out);
+    return rsg::make_boxes(sigma, K, RSG_FIT_SCALED, out);
+}
+
+int rsg_fit_boxes_ex(double sigma, int K, rsg_fit_method method, rsg_boxes* out)
+{
+    return rsg::make_boxes(sigma, K, int(method), out);
 }
 
 int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt, double sigma,
@@ -109,6 +114,30 @@ int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dt
     d.sigma = sigma;
     d.K = K;
     d.b = b;
+    d.boxes = nullptr;
+    rsg::ImgParams ip;
+    int rc = rsg::plan_image(d, &ip);
+    if (rc != RSG_OK) return rc;
+    return rsg::launch_single(ip, static_cast<hipStream_t>(stream));
+}
+
+int rsg_box_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt, const rsg_boxes* boxes,
+                   rsg_boundary b, void* stream)
+{
+    if (!boxes) return rsg::set_error(RSG_EINVAL, "boxes is NULL");
+    rsg_image_desc d;
+    d.src = d_src;
+    d.dst = d_dst;
+    d.H = H;
+    d.W = W;
+    d.C = C;
+    d.src_stride = 0;
+    d.dst_stride = 0;
+    d.dt = dt;
+    d.sigma = boxes->sigma;
+    d.K = boxes->K;
+    d.b = b;
+    d.boxes = boxes;
     rsg::ImgParams ip;
     int rc = rsg::plan_image(d, &ip);
     if (rc != RSG_OK) return rc;

@@ -15,7 +15,8 @@ int set_error(int code, const char* fmt, ...);
 
 // Section 4.2 sigma0 fit (cached per K) and per-sigma boxes.
 int sigma0_fit(int K, bool quadratic_form, int* p, double* c, double* err);
-int make_boxes(double sigma, int K, bool quadratic_form, rsg_boxes* out);
+int make_boxes(double sigma, int K, int method, rsg_boxes* out);   // method: rsg_fit_method
+int check_boxes(const rsg_boxes& b, bool need_u8);                 // caller-supplied boxes
 extern const double kSigma0Value;
 
 constexpr int kWave = 64;          // CDNA wavefront width; also the strip width in samples

@@ -110,6 +110,26 @@ int default_hs(int H, int nstrips, int R, uint32_t lds)
 
 }  // namespace
 
+int check_boxes(const rsg_boxes& b, bool need_u8)
+{
+    if (b.K < 1 || b.K > RSG_MAX_K) return set_error(RSG_EINVAL, "boxes: K must be in 1..5 (got %d)", b.K);
+    int64_t rmax = 0;
+    for (int k = 0; k < b.K; ++k) {
+        if (b.r[k] < 0 || b.r[k] > (1 << 26)) return set_error(RSG_EINVAL, "boxes: half-width %d out of range", b.r[k]);
+        if (!std::isfinite(b.w32[k])) return set_error(RSG_EINVAL, "boxes: weight %d is not finite", k);
+        rmax = std::max<int64_t>(rmax, b.r[k]);
+    }
+    if (need_u8) {
+        if (!b.u8_ok) return set_error(RSG_EUNSUPPORTED, "boxes: no integer weights for uint8");
+        int64_t G = 0;
+        for (int k = 0; k < b.K; ++k) G += int64_t(b.m[k]) * (2 * int64_t(b.r[k]) + 1);
+        if (G <= 0 || uint64_t(G) != b.G || G >= (int64_t(1) << 24) ||
+            int64_t(255) * G * (2 * rmax + 1) >= (int64_t(1) << 32))
+            return set_error(RSG_EINVAL, "boxes: inconsistent or oversized integer weights");
+    }
+    return RSG_OK;
+}
+
 void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_order_relaxed); }
 void set_path_override(int path) { g_path_override.store(path, std::memory_order_relaxed); }
 
@@ -136,8 +156,14 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     }
 
     rsg_boxes b;
-    int rc = make_boxes(d.sigma, d.K, true, &b);
-    if (rc != RSG_OK) return rc;
+    if (d.boxes) {
+        int rc = check_boxes(*d.boxes, d.dt == RSG_U8);
+        if (rc != RSG_OK) return rc;
+        b = *d.boxes;
+    } else {
+        int rc = make_boxes(d.sigma, d.K, RSG_FIT_SCALED, &b);
+        if (rc != RSG_OK) return rc;
+    }
     if (d.dt == RSG_U8 && !b.u8_ok)
         return set_error(RSG_EUNSUPPORTED, "no integer weight scale for uint8 at sigma=%g K=%d", d.sigma, d.K);
 

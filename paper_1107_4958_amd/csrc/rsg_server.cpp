@@ -36,7 +36,9 @@ uint64_t now_ns()
 
 struct Request {
     uint64_t ticket;
-    rsg_image_desc desc;
+    rsg_image_desc desc;           // desc.boxes is NULL here; see boxes below
+    bool own_boxes = false;        // the caller passed boxes: a copy is kept
+    rsg_boxes boxes;
     ImgParams plan;
     size_t footprint;
     rsg_req_stats st;
@@ -79,7 +81,10 @@ namespace {
 void launch_group(rsg_server* s, Slot& slot, std::vector<Request>& group)
 {
     std::vector<rsg_image_desc> descs;
-    for (auto& r : group) descs.push_back(r.desc);
+    for (auto& r : group) {
+        descs.push_back(r.desc);
+        descs.back().boxes = r.own_boxes ? &r.boxes : nullptr;
+    }
     std::vector<ImgParams> imgs;
     std::vector<BatchTask> tasks;
     int rc = plan_batch(descs.data(), int(descs.size()), imgs, tasks);
@@ -233,6 +238,11 @@ int rsg_submit(rsg_server* s, const rsg_image_desc* req, uint64_t* ticket)
     Request r;
     std::memset(&r.st, 0, sizeof(r.st));
     r.desc = *req;
+    if (req->boxes) {                     // the caller's boxes need only live during this call
+        r.own_boxes = true;
+        r.boxes = *req->boxes;
+    }
+    r.desc.boxes = nullptr;
     int rc = plan_image(*req, &r.plan);
     if (rc != RSG_OK) return rc;
     const int es = dtype_size(req->dt);

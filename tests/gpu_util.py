@@ -28,11 +28,11 @@ def decode(img: np.ndarray, dtype: str) -> np.ndarray:
     return img.astype(np.float64)
 
 
-def gpu_filter(img: np.ndarray, dtype: str, sigma: float, K: int, boundary: int = 0) -> np.ndarray:
+def gpu_filter(img: np.ndarray, dtype: str, sigma: float, K: int, boundary: int = 0, boxes=None) -> np.ndarray:
     import torch
     import paper_1107_4958_amd as rsg
     src = to_device(img, dtype)
-    out = rsg.filter_tensor(src, sigma, K, boundary)
+    out = rsg.filter_tensor(src, sigma, K, boundary, boxes=boxes)
     torch.cuda.synchronize()
     return from_device(out, dtype)
 

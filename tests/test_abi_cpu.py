@@ -21,7 +21,7 @@ def _rsg():
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "rsg.h")).read()
     declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(rsg_\w+)\s*\(", header, re.M))
-    assert len(declared) == 12
+    assert len(declared) == 14
     rsg = _rsg()
     lib = ctypes.CDLL(rsg.LIB_PATH)
     for name in declared:
@@ -142,3 +142,78 @@ def test_one_hip_runtime_per_process():
                          env=dict(os.environ, PYTHONPATH=ROOT))
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+# --------------------------------------------------------------------------
+# Fit methods and caller-supplied boxes (host only)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("sigma,K", [(0.5, 5), (0.8, 3), (1.0, 4), (2.0, 3), (3.7, 5), (8.0, 4), (12.0, 5),
+                                     (100.0 / math.pi, 3)])
+def test_direct_fit_matches_oracle(sigma, K):
+    """The product's direct fit at sigma against the oracle's (independent
+    code): partition, half-widths and uint8 form exact, weights to rounding."""
+    import oracle
+    rsg = _rsg()
+    b = rsg.rsg_fit_boxes_ex(sigma, K, rsg.RSG_FIT_DIRECT)
+    o = oracle.boxes_direct(sigma, K)
+    assert list(b.p[:K]) == list(o["p"]) and list(b.r[:K]) == list(o["r"])
+    # two independent Cholesky solves: agreement to rounding, absolutely for
+    # the vanishing weights of an exact fit at small sigma (c_k = g(k))
+    assert np.allclose(np.array(b.w[:K]), o["w"], rtol=1e-11, atol=1e-13)
+    assert np.allclose(np.array(b.w32[:K], dtype=np.float32), o["w32"], rtol=2 ** -23, atol=1e-13)
+    assert bool(b.u8_ok) == (o["m"] is not None)
+    if b.u8_ok:
+        assert list(b.m[:K]) == list(o["m"]) and b.G == o["G"] and b.s == o["s"]
+
+
+@pytest.mark.parametrize("sigma,K", [(2.0, 3), (8.0, 4), (30.0, 5)])
+def test_scaled_l2_fit_matches_oracle(sigma, K):
+    import oracle
+    rsg = _rsg()
+    b = rsg.rsg_fit_boxes_ex(sigma, K, rsg.RSG_FIT_SCALED_L2)
+    o = oracle.boxes(sigma, K, use_qf=False)
+    assert list(b.p[:K]) == list(o["p"]) and list(b.r[:K]) == list(o["r"])
+    assert np.allclose(np.array(b.w[:K]), o["w"], rtol=1e-11, atol=0)
+    s = rsg.rsg_fit_boxes_ex(sigma, K, rsg.RSG_FIT_SCALED)
+    r = rsg.rsg_fit_boxes(sigma, K)
+    assert list(s.r[:K]) == list(r.r[:K]) and list(s.w[:K]) == list(r.w[:K])
+
+
+def test_fit_method_errors():
+    rsg = _rsg()
+    with pytest.raises(rsg.RsgError) as e:
+        rsg.rsg_fit_boxes_ex(2.0, 3, 7)
+    assert e.value.code == rsg.RSG_EINVAL
+    with pytest.raises(rsg.RsgError) as e:
+        rsg.rsg_fit_boxes_ex(40.0, 3, rsg.RSG_FIT_DIRECT)
+    assert e.value.code == rsg.RSG_EUNSUPPORTED
+
+
+def test_caller_boxes_are_validated():
+    """Descriptors carrying boxes: planned like the fitted ones when valid,
+    refused when inconsistent (checked on the host, nothing launched)."""
+    rsg = _rsg()
+    d = rsg.rsg_image_desc()
+    d.src, d.dst = 0x10000, 0x100000000000
+    d.H, d.W, d.C = 300, 200, 1
+    d.dt, d.sigma, d.K, d.b = rsg.RSG_U8, 2.0, 3, rsg.RSG_REPLICATE
+    base = rsg.rsg_plan_shape(d)
+    b = rsg.rsg_fit_boxes(2.0, 3)
+    d.boxes = ctypes.addressof(b)
+    assert rsg.rsg_plan_shape(d) == base
+    bad = rsg.rsg_boxes.from_buffer_copy(b)
+    bad.G = bad.G + 1                                  # G no longer sum m_k (2 r_k + 1)
+    d.boxes = ctypes.addressof(bad)
+    with pytest.raises(rsg.RsgError) as e:
+        rsg.rsg_plan_shape(d)
+    assert e.value.code == rsg.RSG_EINVAL
+    bad = rsg.rsg_boxes.from_buffer_copy(b)
+    bad.r[1] = -1
+    d.boxes = ctypes.addressof(bad)
+    with pytest.raises(rsg.RsgError):
+        rsg.rsg_plan_shape(d)
+    bad = rsg.rsg_boxes.from_buffer_copy(b)
+    bad.K = 0
+    d.boxes = ctypes.addressof(bad)
+    with pytest.raises(rsg.RsgError):
+        rsg.rsg_plan_shape(d)

@@ -273,3 +273,54 @@ def test_batch_two_pass_identical_to_alone():
                 _spot_check(it["img"], got, it["dtype"], it["sigma"], it["K"])
     finally:
         rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+
+
+def test_caller_boxes_in_batch_and_server():
+    """Descriptors with their own boxes (direct fit) in one batch and through
+    the server (the boxes struct is released right after submit): the same
+    bits as rsg_box_filter alone, and the oracle's direct fit on samples."""
+    import gc
+    import torch
+    rsg = _rsg()
+    items = _mixed_images()[:8]
+    srcs = [to_device(it["img"], it["dtype"]) for it in items]
+    fits = [rsg.rsg_fit_boxes_ex(min(it["sigma"], 30.0), it["K"], rsg.RSG_FIT_DIRECT) for it in items]
+    alone = [from_device(rsg.filter_tensor(s, 0, 0, boxes=b), it["dtype"]) for s, b, it in zip(srcs, fits, items)]
+    torch.cuda.synchronize()
+    dsts = [torch.full_like(s, 0) for s in srcs]
+    descs = [rsg.make_desc(s, d, it["sigma"], it["K"], boxes=b) for s, d, it, b in zip(srcs, dsts, items, fits)]
+    need = rsg.rsg_filter_batch_workspace(descs)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rsg.rsg_filter_batch(descs, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    for it, d, a in zip(items, dsts, alone):
+        assert np.array_equal(from_device(d, it["dtype"]).view(np.uint8), a.view(np.uint8))
+    arena = torch.empty(32 << 20, dtype=torch.uint8, device="cuda")
+    sdsts = [torch.full_like(s, 0) for s in srcs]
+    torch.cuda.synchronize()
+    srv = _server(arena)
+    try:
+        tickets = []
+        for s, d, it in zip(srcs, sdsts, items):
+            b = rsg.rsg_fit_boxes_ex(min(it["sigma"], 30.0), it["K"], rsg.RSG_FIT_DIRECT)
+            tickets.append(rsg.rsg_submit(srv, rsg.make_desc(s, d, it["sigma"], it["K"], boxes=b)))
+            del b
+            gc.collect()
+        stats = _wait_all(srv, tickets)
+        assert all(v[0] == rsg.RSG_OK for v in stats.values())
+    finally:
+        rsg.rsg_server_destroy(srv)
+    for it, d, a in zip(items, sdsts, alone):
+        assert np.array_equal(from_device(d, it["dtype"]).view(np.uint8), a.view(np.uint8))
+    import oracle
+    for it, a in zip(items, alone):
+        if it["dtype"] != "u8":
+            continue
+        o = oracle.boxes_direct(min(it["sigma"], 30.0), it["K"])
+        im3 = it["img"][..., None] if it["img"].ndim == 2 else it["img"]
+        a3 = a[..., None] if a.ndim == 2 else a
+        rng = np.random.default_rng(1)
+        H, W, C = im3.shape
+        ys, xs, cs = rng.integers(0, H, 100), rng.integers(0, W, 100), rng.integers(0, C, 100)
+        ref = oracle.box_filter_u8_points(im3, o["r"], o["m"], o["G"], ys, xs, cs)
+        assert np.array_equal(a3[ys, xs, cs], ref)

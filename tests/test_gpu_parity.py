@@ -230,3 +230,31 @@ def test_one_wave_fused_form(dtype, H, W, C, sigma, K, boundary):
         _check(img, dtype, sigma, K, boundary)
     finally:
         rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+
+
+# --------------------------------------------------------------------------
+# Other fit methods: the direct fit at sigma and the l2 fit, through
+# rsg_box_filter, against the oracle's own fit of the same method
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+@pytest.mark.parametrize("method,sigma,K", [("direct", 0.5, 5), ("direct", 1.0, 3), ("direct", 2.5, 4),
+                                            ("direct", 6.0, 5), ("l2", 2.0, 3), ("l2", 9.0, 5)])
+@pytest.mark.parametrize("H,W,C,boundary", [(130, 77, 3, 0), (257, 259, 1, 2), (33, 520, 2, 1)])
+def test_fit_methods_filter(dtype, method, sigma, K, H, W, C, boundary):
+    import paper_1107_4958_amd as rsg
+    img = synthimg.image(H, W, C, dtype, 53)
+    if method == "direct":
+        b = rsg.rsg_fit_boxes_ex(sigma, K, rsg.RSG_FIT_DIRECT)
+        o = oracle.boxes_direct(sigma, K)
+    else:
+        b = rsg.rsg_fit_boxes_ex(sigma, K, rsg.RSG_FIT_SCALED_L2)
+        o = oracle.boxes(sigma, K, use_qf=False)
+    out = gpu_filter(img, dtype, sigma, K, boundary, boxes=b)
+    if dtype == "u8":
+        if o["m"] is None:
+            pytest.skip("no integer weights for these boxes")
+        ref = oracle.box_filter_u8(img, o["r"], o["m"], o["G"], boundary)
+        assert np.array_equal(out, ref)
+    else:
+        ref = oracle.box_filter(decode(img, dtype), o["r"], o["w32"].astype(np.float64), boundary)
+        assert rel_max_err(out, ref) <= FP32_TOL
