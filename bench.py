@@ -224,6 +224,57 @@ def fit_study():
     return out
 
 
+def strided_workload(steps):
+    """Strided (downsampling) evaluation at 8192 x 8192 FP32, sigma = 8,
+    K = 3: every step-th row and pixel for step in {1, 2, 4} (step 1 through
+    the same two-pass path), against the full single-image filter.
+    Algorithmic bytes: the input read once plus the strided output written
+    once; sampled parity against the oracle."""
+    import torch
+    import oracle
+    import paper_1107_4958_amd as rsg
+    import synthimg
+    H = W = 8192
+    img = synthimg.to_dtype(synthimg.one_over_f(H, W, 13), "f32")
+    base = to_dev(img, "f32")
+    srcs = [base, base.clone(), base.clone()]
+    stream = torch.cuda.current_stream()
+    b = oracle.boxes(8.0, 3)
+    rng = np.random.default_rng(9)
+    out = []
+    ms_full, _ = time_image(img, "f32", 8.0, 3, steps, 3, min_pool_bytes=1 << 30)
+    for step in (1, 2, 4):
+        Ho, Wo = (H + step - 1) // step, (W + step - 1) // step
+        dsts = [torch.empty((Ho, Wo), dtype=torch.float32, device="cuda") for _ in srcs]
+
+        def launch(i):
+            rsg.rsg_gauss_filter_strided(srcs[i % 3].data_ptr(), dsts[i % 3].data_ptr(), H, W, 1, rsg.RSG_F32, 8.0,
+                                         3, None, rsg.RSG_REPLICATE, step, stream.cuda_stream)
+
+        for i in range(3):
+            launch(i)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            launch(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        o = dsts[(steps - 1) % 3].cpu().numpy()
+        ys, xs = rng.integers(0, Ho, 400), rng.integers(0, Wo, 400)
+        ref = oracle.box_filter_points(img[..., None].astype(np.float64), b["r"], b["w32"].astype(np.float64),
+                                       ys * step, xs * step)
+        err = float(np.max(np.abs(o[ys, xs] - ref)) / np.max(np.abs(img)))
+        alg = 4.0 * (H * W + Ho * Wo)
+        out.append({"step": step, "ms": round(ms, 5), "input_gpix_s": round(H * W / (ms * 1e-3) / 1e9, 2),
+                    "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "vs_full_filter": round(ms_full / ms, 3), "parity_max_rel_err": float("%.3g" % err)})
+        del dsts
+    return {"H": H, "W": W, "sigma": 8.0, "K": 3, "ms_full_filter": round(ms_full, 5), "steps": out}
+
+
 def sigma_k_grid(imgs, steps):
     """Gpixel/s and HBM fraction at 4096^2 for sigma in {2, 8, 32}, K in {3, 4, 5}."""
     out = []
@@ -497,6 +548,8 @@ def main():
         result["plain_512"] = plain_workload(200)
         print("bench: fit methods", file=sys.stderr, flush=True)
         result["fit_study_1024"] = fit_study()
+        print("bench: strided", file=sys.stderr, flush=True)
+        result["strided_8192"] = strided_workload(20)
         print("bench: batch", file=sys.stderr, flush=True)
         result["batch"] = batch_workload(5, gpx if args.dtype == "f32" else None)
         print("bench: precision", file=sys.stderr, flush=True)

@@ -138,6 +138,21 @@ int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dt
 int rsg_box_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt,
                    const rsg_boxes* boxes, rsg_boundary b, void* stream);
 
+/* Strided (downsampling) evaluation: the filtered image at every step-th row
+ * and pixel only, out(i, j, c) = filtered(i step, j step, c), written as a
+ * contiguous ceil(H/step) x ceil(W/step) x C image to d_dst (Eq. indep
+ * evaluated on a sparser output grid, Section 3.3; the running sums still
+ * cover every input sample).  Boxes: `boxes` if not NULL (as
+ * rsg_box_filter), else rsg_fit_boxes(sigma, K).  For step > 1 it runs on
+ * the two-pass path (row filter keeping every step-th pixel into an
+ * intermediate of ceil(W/step) C x H four-byte words, then the column filter
+ * keeping every step-th row); step = 1 is rsg_gauss_filter / rsg_box_filter.
+ * Errors: as rsg_gauss_filter / rsg_box_filter; RSG_EINVAL (step < 1);
+ * RSG_EUNSUPPORTED (boxes too wide for the two-pass path: C = 3 beyond
+ * r_max ~ 127, C = 4 beyond ~ 95). */
+int rsg_gauss_filter_strided(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt, double sigma,
+                             int K, const rsg_boxes* boxes, rsg_boundary b, int step, void* stream);
+
 /* One image of a batch; strides in elements (0 means W*C). */
 typedef struct {
     const void* src;

@@ -107,7 +107,8 @@ class rsg_req_stats(ctypes.Structure):
 
 SYMBOLS = ("rsg_fit_boxes", "rsg_gauss_filter", "rsg_filter_batch_workspace", "rsg_filter_batch",
            "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_plan_shape",
-           "rsg_tune_override", "rsg_tune_path", "rsg_fit_boxes_ex", "rsg_box_filter", "rsg_last_error")
+           "rsg_tune_override", "rsg_tune_path", "rsg_fit_boxes_ex", "rsg_box_filter", "rsg_gauss_filter_strided",
+           "rsg_last_error")
 
 
 def _load():
@@ -130,6 +131,7 @@ def _load():
     lib.rsg_gauss_filter.argtypes = [V, V, I, I, I, I, D, I, I, V]
     lib.rsg_fit_boxes_ex.argtypes = [D, I, I, ctypes.POINTER(rsg_boxes)]
     lib.rsg_box_filter.argtypes = [V, V, I, I, I, I, ctypes.POINTER(rsg_boxes), I, V]
+    lib.rsg_gauss_filter_strided.argtypes = [V, V, I, I, I, I, D, I, ctypes.POINTER(rsg_boxes), I, I, V]
     lib.rsg_filter_batch_workspace.argtypes = [ctypes.POINTER(rsg_image_desc), I, ctypes.POINTER(S)]
     lib.rsg_filter_batch.argtypes = [ctypes.POINTER(rsg_image_desc), I, V, S, V]
     lib.rsg_server_create.argtypes = [ctypes.POINTER(rsg_server_config), ctypes.POINTER(V)]
@@ -275,6 +277,31 @@ def _stream_handle(t, stream):
     if stream is None:
         return torch.cuda.current_stream(t.device).cuda_stream
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def rsg_gauss_filter_strided(d_src: int, d_dst: int, H: int, W: int, C: int, dt: int, sigma: float, K: int,
+                             boxes=None, boundary: int = RSG_REPLICATE, step: int = 1, stream: int = 0) -> None:
+    _check(_lib.rsg_gauss_filter_strided(ctypes.c_void_p(d_src), ctypes.c_void_p(d_dst), H, W, C, dt, float(sigma),
+                                         int(K), ctypes.byref(boxes) if boxes is not None else None, boundary,
+                                         int(step), ctypes.c_void_p(stream)))
+
+
+def filter_strided_tensor(src, sigma: float, K: int, step: int, boundary: int = RSG_REPLICATE, out=None,
+                          stream=None, boxes=None):
+    """Every step-th row and pixel of the filtered image, as a new
+    ceil(H/step) x ceil(W/step) (x C) tensor (or into `out`)."""
+    import torch
+    if not src.is_cuda or not src.is_contiguous():
+        raise ValueError("src must be a contiguous device tensor")
+    H, W, C = _hwc(src)
+    shape = ((H + step - 1) // step, (W + step - 1) // step) + ((C,) if src.dim() == 3 else ())
+    if out is None:
+        out = torch.empty(shape, dtype=src.dtype, device=src.device)
+    elif tuple(out.shape) != shape or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of shape %r" % (shape,))
+    rsg_gauss_filter_strided(src.data_ptr(), out.data_ptr(), H, W, C, tensor_dtype_code(src), sigma, K, boxes,
+                             boundary, step, _stream_handle(src, stream))
+    return out
 
 
 def filter_tensor(src, sigma: float, K: int, boundary: int = RSG_REPLICATE, out=None, stream=None, boxes=None):

@@ -121,6 +121,28 @@ int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dt
     return rsg::launch_single(ip, static_cast<hipStream_t>(stream));
 }
 
+int rsg_gauss_filter_strided(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt, double sigma,
+                             int K, const rsg_boxes* boxes, rsg_boundary b, int step, void* stream)
+{
+    rsg_image_desc d;
+    d.src = d_src;
+    d.dst = d_dst;
+    d.H = H;
+    d.W = W;
+    d.C = C;
+    d.src_stride = 0;
+    d.dst_stride = 0;
+    d.dt = dt;
+    d.sigma = boxes ? boxes->sigma : sigma;
+    d.K = boxes ? boxes->K : K;
+    d.b = b;
+    d.boxes = boxes;
+    rsg::ImgParams ip;
+    int rc = rsg::plan_image(d, &ip, step);
+    if (rc != RSG_OK) return rc;
+    return rsg::launch_single(ip, static_cast<hipStream_t>(stream));
+}
+
 int rsg_box_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt, const rsg_boxes* boxes,
                    rsg_boundary b, void* stream)
 {

@@ -61,6 +61,7 @@ struct ImgParams {
     uint32_t lds_one;              // dynamic LDS of the one-wave fused form (batches, serving)
     // two-pass path (wide boxes): row filter + transposed store, twice
     int32_t path;                  // kPathFused or kPathTwoPass
+    int32_t step;                  // output stride in pixels along both axes (1: every pixel; two-pass only)
     int32_t pc;                    // fused path: 1 = producer / consumer workgroups of two waves
     int32_t pnpl[2];               // samples per lane of pass A, pass B
     int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
@@ -91,6 +92,8 @@ struct PassParams {
     int32_t vec;                   // rows allow 16-byte chunk loads
     int32_t win_pitch;             // LDS words per wave window
     int32_t win_shift;             // window start offset (aligns its new part to 16 bytes)
+    int32_t ostep;                 // store every ostep-th pixel of a row (1: all), compacted
+    double inv_ostep;              // 1.0 / ostep
 };
 
 // One unit of work of a batched launch.
@@ -100,7 +103,7 @@ struct BatchTask {
 };
 
 // Plan for one image: validates, fits (cached), picks the tile shape.
-int plan_image(const rsg_image_desc& d, ImgParams* ip);
+int plan_image(const rsg_image_desc& d, ImgParams* ip, int step = 1);   // step > 1: strided output, two-pass
 // Process-wide segment height that overrides the tuning table (0: none).
 void set_hs_override(int hs);
 // Process-wide path override (0: planner's choice, 1: fused, 2: two-pass).

@@ -30,7 +30,11 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
     std::memset(&pp, 0, sizeof(pp));
     const int es = dtype_size(ip.dtype);
     const int WC = ip.W * ip.C;
+    const int step = ip.step > 1 ? ip.step : 1;
+    const int WoC = (ip.W + step - 1) / step * ip.C;   // intermediate rows: kept pixels x channels
     const int npl = ip.pnpl[pass];
+    pp.ostep = step;
+    pp.inv_ostep = 1.0 / double(step);
     if (pass == 0) {                       // image rows -> intermediate (W*C) x H
         pp.src = ip.src;
         pp.dst = mid;
@@ -48,7 +52,7 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
         pp.dst = ip.dst;
         pp.src_stride = ip.H;
         pp.dst_stride = ip.dst_stride;
-        pp.rows = WC;
+        pp.rows = WoC;
         pp.len = ip.H;
         pp.vec = (int64_t(ip.H) * 4) % 16 == 0;
     }
@@ -76,7 +80,8 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
 int launch_two_pass(const ImgParams& ip, hipStream_t stream)
 {
     void* mid = nullptr;
-    const size_t bytes = size_t(ip.H) * size_t(ip.W) * size_t(ip.C) * 4;
+    const int step = ip.step > 1 ? ip.step : 1;
+    const size_t bytes = size_t(ip.H) * size_t((ip.W + step - 1) / step) * size_t(ip.C) * 4;
     if (hipMallocAsync(&mid, bytes, stream) != hipSuccess)
         return set_error(RSG_ENOMEM, "cannot allocate the %zu-byte intermediate of the two-pass path", bytes);
     int rc = launch_pass(ip, 0, pass_params(ip, 0, mid), stream);

@@ -133,8 +133,9 @@ int check_boxes(const rsg_boxes& b, bool need_u8)
 void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_order_relaxed); }
 void set_path_override(int path) { g_path_override.store(path, std::memory_order_relaxed); }
 
-int plan_image(const rsg_image_desc& d, ImgParams* ip)
+int plan_image(const rsg_image_desc& d, ImgParams* ip, int step)
 {
+    if (step < 1) return set_error(RSG_EINVAL, "output step must be >= 1 (got %d)", step);
     if (!d.src || !d.dst) return set_error(RSG_EINVAL, "NULL image pointer");
     if (d.H < 1 || d.W < 1) return set_error(RSG_EINVAL, "H and W must be >= 1 (got %d x %d)", d.H, d.W);
     if (d.C < 1 || d.C > 4) return set_error(RSG_EINVAL, "C must be in 1..4 (got %d)", d.C);
@@ -143,15 +144,18 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         return set_error(RSG_EINVAL, "bad boundary %d", int(d.b));
     const int64_t WC = int64_t(d.W) * d.C;
     if (WC > (int64_t(1) << 30) || d.H > (1 << 30)) return set_error(RSG_EUNSUPPORTED, "image too large");
+    // the output: every step-th row and pixel, (Ho x Wo x C)
+    const int64_t Ho = (d.H + step - 1) / step;
+    const int64_t WoC = int64_t((d.W + step - 1) / step) * d.C;
     const int64_t ss = d.src_stride ? d.src_stride : WC;
-    const int64_t ds = d.dst_stride ? d.dst_stride : WC;
-    if (ss < WC || ds < WC) return set_error(RSG_EINVAL, "row stride smaller than W*C");
+    const int64_t ds = d.dst_stride ? d.dst_stride : WoC;
+    if (ss < WC || ds < WoC) return set_error(RSG_EINVAL, "row stride smaller than the row");
     const int es = dtype_size(d.dt);
     {   // source and destination must not overlap
         const char* s0 = static_cast<const char*>(d.src);
         const char* s1 = s0 + (int64_t(d.H - 1) * ss + WC) * es;
         const char* t0 = static_cast<const char*>(d.dst);
-        const char* t1 = t0 + (int64_t(d.H - 1) * ds + WC) * es;
+        const char* t1 = t0 + ((Ho - 1) * ds + WoC) * es;
         if (s0 < t1 && t0 < s1) return set_error(RSG_EINVAL, "source and destination overlap");
     }
 
@@ -219,7 +223,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
     const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t);
     bool two = two_ok && (tabled ? hs_t < 0 : R * C >= kTwoPassMinRC);
     if (ov == 1 || ov == 3) two = false;
-    if (ov == 2) {
+    if (ov == 2 || step > 1) {      // strided output exists on the two-pass path only
         if (!two_ok) return set_error(RSG_EUNSUPPORTED, "two-pass path: box half-width %d too wide for C=%d", R, C);
         two = true;
     }
@@ -251,7 +255,8 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip)
         p.nstrips = int((WC + kWave - 1) / kWave);
         p.hs = d.H;
         p.nsegs = 1;
-        p.ntasks = (d.H + kPassRowsHost - 1) / kPassRowsHost + int((WC + kPassRowsHost - 1) / kPassRowsHost);
+        p.step = step;
+        p.ntasks = (d.H + kPassRowsHost - 1) / kPassRowsHost + int((WoC + kPassRowsHost - 1) / kPassRowsHost);
         p.lds_bytes = std::max(p.plds[0], p.plds[1]);
         *ip = p;
         return RSG_OK;

@@ -264,14 +264,30 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
         }
         __syncthreads();
 
-        // transposed store: element (x, row0 + w) for x = k CW - R C + o
+        // transposed store: element (x, row0 + w) for x = k CW - R C + o; a
+        // strided pass keeps pixels x / C = 0, ostep, 2 ostep, ... and stores
+        // pixel j ostep at j (channels kept)
         const int x0 = k * CW - R * C;
+        const int ostep = p.ostep;
         for (int idx = threadIdx.x; idx < CW * TR; idx += TR * kWave) {
             const int o = idx / TR;
             const int w = idx % TR;
             const int x = x0 + o;
-            if (x >= 0 && x < len && row0 + w < p.rows)
-                store_pass_out<OUT>(p.dst, int64_t(x) * p.dst_stride + row0 + w, stg[o * SP + w]);
+            if (x >= 0 && x < len && row0 + w < p.rows) {
+                int xo = x;
+                if (ostep > 1) {
+                    // px = q ostep + rem: an FP64 reciprocal estimate (off by
+                    // at most one for px < 2^31) and one correction
+                    const int px = x / C;
+                    int q = int(double(px) * p.inv_ostep);
+                    int rem = px - q * ostep;
+                    if (rem < 0) { --q; rem += ostep; }
+                    else if (rem >= ostep) { ++q; rem -= ostep; }
+                    if (rem) continue;
+                    xo = q * C + (x - px * C);
+                }
+                store_pass_out<OUT>(p.dst, int64_t(xo) * p.dst_stride + row0 + w, stg[o * SP + w]);
+            }
         }
         // with two staging tiles the next chunk writes the other one; the
         // barrier of that chunk orders this chunk's reads before its reuse

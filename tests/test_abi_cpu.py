@@ -21,7 +21,7 @@ def _rsg():
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "rsg.h")).read()
     declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(rsg_\w+)\s*\(", header, re.M))
-    assert len(declared) == 14
+    assert len(declared) == 15
     rsg = _rsg()
     lib = ctypes.CDLL(rsg.LIB_PATH)
     for name in declared:
@@ -217,3 +217,13 @@ def test_caller_boxes_are_validated():
     d.boxes = ctypes.addressof(bad)
     with pytest.raises(rsg.RsgError):
         rsg.rsg_plan_shape(d)
+
+
+def test_strided_validation():
+    """Refusals of the strided entry point happen on the host, before any launch."""
+    rsg = _rsg()
+    lib = rsg.lib()
+    A, B = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x9000000)
+    assert lib.rsg_gauss_filter_strided(A, B, 64, 64, 1, rsg.RSG_F32, 2.0, 3, None, 0, 0, None) == rsg.RSG_EINVAL
+    assert lib.rsg_gauss_filter_strided(A, B, 64, 64, 4, rsg.RSG_F32, 60.0, 5, None, 0, 2, None) == rsg.RSG_EUNSUPPORTED
+    assert lib.rsg_gauss_filter_strided(None, B, 64, 64, 1, rsg.RSG_F32, 2.0, 3, None, 0, 2, None) == rsg.RSG_EINVAL

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synthimg
-from gpu_util import decode, gpu_filter, half_ulp_diff, rel_max_err
+from gpu_util import decode, from_device, gpu_filter, half_ulp_diff, rel_max_err, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -258,3 +258,70 @@ def test_fit_methods_filter(dtype, method, sigma, K, H, W, C, boundary):
     else:
         ref = oracle.box_filter(decode(img, dtype), o["r"], o["w32"].astype(np.float64), boundary)
         assert rel_max_err(out, ref) <= FP32_TOL
+
+
+# --------------------------------------------------------------------------
+# Strided (downsampling) evaluation: every step-th row and pixel
+# --------------------------------------------------------------------------
+STRIDED = [
+    (1, 1, 1, 2.0, 3, 0, 2), (7, 5, 1, 1.5, 3, 0, 3), (257, 259, 1, 8.0, 5, 1, 2), (130, 77, 3, 6.0, 4, 2, 3),
+    (97, 250, 2, 4.0, 4, 0, 4), (33, 2000, 4, 5.0, 3, 0, 7), (300, 17, 1, 20.0, 5, 0, 16), (64, 64, 1, 3.0, 3, 0, 100),
+    (200, 333, 1, 8.0, 3, 2, 1),
+]
+
+
+def _strided_gpu(img, dtype, sigma, K, boundary, step, boxes=None):
+    import torch
+    import paper_1107_4958_amd as rsg
+    src = to_device(img, dtype)
+    out = rsg.filter_strided_tensor(src, sigma, K, step, boundary, boxes=boxes)
+    torch.cuda.synchronize()
+    return from_device(out, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32", "f16"])
+@pytest.mark.parametrize("H,W,C,sigma,K,boundary,step", STRIDED)
+def test_strided_output(dtype, H, W, C, sigma, K, boundary, step):
+    img = synthimg.image(H, W, C, dtype, 59)
+    out = _strided_gpu(img, dtype, sigma, K, boundary, step)
+    b = oracle.boxes(sigma, K)
+    if dtype == "u8":
+        ref = oracle.box_filter_u8(img, b["r"], b["m"], b["G"], boundary)[::step, ::step]
+        assert out.shape == ref.shape and np.array_equal(out, ref)
+        return
+    ref = oracle.box_filter(decode(img, dtype), b["r"], b["w32"].astype(np.float64), boundary)[::step, ::step]
+    assert out.shape == ref.shape
+    if dtype == "f32":
+        assert rel_max_err(out, ref) <= FP32_TOL
+    else:
+        assert half_ulp_diff(out, ref, dtype) <= 1
+
+
+def test_strided_step1_and_direct_boxes():
+    """step = 1 reproduces the single-image result (uint8: bit for bit), and
+    caller boxes pass through."""
+    import paper_1107_4958_amd as rsg
+    img = synthimg.image(211, 190, 3, "u8", 61)
+    assert np.array_equal(_strided_gpu(img, "u8", 7.0, 4, 0, 1), gpu_filter(img, "u8", 7.0, 4, 0))
+    b = rsg.rsg_fit_boxes_ex(1.2, 4, rsg.RSG_FIT_DIRECT)
+    o = oracle.boxes_direct(1.2, 4)
+    out = _strided_gpu(img, "u8", 0.0, 0, 2, 3, boxes=b)
+    assert np.array_equal(out, oracle.box_filter_u8(img, o["r"], o["m"], o["G"], 2)[::3, ::3])
+
+
+@pytest.mark.parametrize("dtype,step", [("f32", 2), ("u8", 4)])
+def test_strided_at_scale_4096(dtype, step):
+    b = oracle.boxes(8.0, 3)
+    img = synthimg.image(4096, 4096, 1, dtype, seed=2)
+    out = _strided_gpu(img, dtype, 8.0, 3, 0, step)
+    Ho, Wo = out.shape
+    ys, xs, _ = _sample_points(Ho, Wo, 1, 800, 5)
+    img3 = img[..., None]
+    cs = np.zeros_like(ys)
+    if dtype == "u8":
+        ref = oracle.box_filter_u8_points(img3, b["r"], b["m"], b["G"], ys * step, xs * step, cs)
+        assert np.array_equal(out[ys, xs], ref)
+    else:
+        ref = oracle.box_filter_points(img3.astype(np.float64), b["r"], b["w32"].astype(np.float64),
+                                       ys * step, xs * step, cs)
+        assert float(np.max(np.abs(out[ys, xs] - ref))) / float(np.max(np.abs(img))) <= FP32_TOL
