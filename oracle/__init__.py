@@ -79,13 +79,15 @@ def _load():
         lib.orc_scale.argtypes = [D, D, I, P, P, P, P, P]
         lib.orc_quant_u8.argtypes = [I, P, P, P, P, P]
         lib.orc_box_f64.argtypes = [P, I, I, I, I, P, P, I, P]
+        lib.orc_box3_f64.argtypes = [P, I, I, I, I, I, P, P, I, P]
         lib.orc_box_u8.argtypes = [P, I, I, I, I, P, P, ctypes.c_int64, I, P]
         lib.orc_gauss_f64.argtypes = [P, I, I, I, D, I, P]
         lib.orc_box_f64_points.argtypes = [P, I, I, I, I, P, P, I, I, P, P, P, P]
         lib.orc_box_u8_points.argtypes = [P, I, I, I, I, P, P, ctypes.c_int64, I, I, P, P, P, P]
         lib.orc_gauss_f64_points.argtypes = [P, I, I, I, D, I, I, P, P, P, P]
         for f in ("orc_eval_partition", "orc_fit", "orc_scale", "orc_quant_u8", "orc_box_f64",
-                  "orc_box_u8", "orc_gauss_f64", "orc_box_f64_points", "orc_box_u8_points", "orc_gauss_f64_points"):
+                  "orc_box_u8", "orc_gauss_f64", "orc_box_f64_points", "orc_box_u8_points", "orc_gauss_f64_points",
+                  "orc_box3_f64"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
         return lib
@@ -219,6 +221,22 @@ def box_filter(img: np.ndarray, r, w, boundary: int = REPLICATE) -> np.ndarray:
     rc = _load().orc_box_f64(_ptr(src), H, W, C, len(r), _ptr(r), _ptr(w), boundary, _ptr(dst))
     if rc != 0:
         raise ValueError("orc_box_f64 failed")
+    return dst
+
+
+def box_filter_3d(vol: np.ndarray, r, w, boundary: int = REPLICATE) -> np.ndarray:
+    """FP64 direct box sums of a D x H x W (x C) volume along all three axes."""
+    if vol.ndim not in (3, 4):
+        raise ValueError("volume must be DxHxW or DxHxWxC")
+    D, H, W = vol.shape[:3]
+    C = vol.shape[3] if vol.ndim == 4 else 1
+    src = np.ascontiguousarray(vol, dtype=np.float64)
+    dst = np.empty_like(src)
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    rc = _load().orc_box3_f64(_ptr(src), D, H, W, C, len(r), _ptr(r), _ptr(w), boundary, _ptr(dst))
+    if rc != 0:
+        raise ValueError("orc_box3_f64 failed")
     return dst
 
 

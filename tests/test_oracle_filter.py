@@ -244,3 +244,51 @@ def test_gauss_points_match_full_filter():
         full = oracle.gauss_filter(img, 3.5, boundary)
         pts = oracle.gauss_filter_points(img, 3.5, ys, xs, cs, boundary=boundary)
         assert np.max(np.abs(pts - full[ys, xs, cs])) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# Volumes: one more separable pass along z
+# --------------------------------------------------------------------------
+def _brute_3d(vol, h, boundary):
+    """Direct 3D correlation with the outer product h x h x h."""
+    R = (len(h) - 1) // 2
+    mode = PAD_MODE[boundary]
+    v = vol.astype(np.float64)
+    if v.ndim == 3:
+        v = v[..., None]
+    x = np.pad(v, ((R, R), (R, R), (R, R), (0, 0)), mode=mode)
+    D, H, W = v.shape[:3]
+    out = np.zeros(v.shape, dtype=np.float64)
+    for dz in range(-R, R + 1):
+        for dy in range(-R, R + 1):
+            for dx in range(-R, R + 1):
+                out += h[dz + R] * h[dy + R] * h[dx + R] * x[R + dz:R + dz + D, R + dy:R + dy + H, R + dx:R + dx + W]
+    return out.reshape(vol.shape)
+
+
+@pytest.mark.parametrize("D,H,W,C", [(1, 1, 1, 1), (5, 3, 4, 1), (7, 6, 5, 2), (9, 4, 11, 3), (2, 13, 1, 1)])
+@pytest.mark.parametrize("boundary", BOUNDARIES)
+@pytest.mark.parametrize("sigma,k", [(1.0, 3), (2.5, 4)])
+def test_box3_equals_3d_brute_force(D, H, W, C, boundary, sigma, k):
+    b = oracle.boxes(sigma, k)
+    rng = np.random.default_rng(D * 100 + H * 10 + W + C)
+    vol = rng.uniform(0, 255, size=(D, H, W, C) if C > 1 else (D, H, W))
+    out = oracle.box_filter_3d(vol, b["r"], b["w"], boundary)
+    ref = _brute_3d(vol, oracle.kernel_1d(b["r"], b["w"]), boundary)
+    assert np.max(np.abs(out - ref)) <= 1e-11 * 255
+
+
+def test_box3_matches_scipy_and_constant():
+    """Three scipy 1D correlations (reflect mode) on a larger volume; a
+    constant volume maps to itself."""
+    b = oracle.boxes(3.0, 3)
+    h = oracle.kernel_1d(b["r"], b["w"])
+    rng = np.random.default_rng(5)
+    vol = rng.uniform(0, 255, size=(12, 20, 17))
+    ref = vol.copy()
+    for ax in range(3):
+        ref = ndimage.correlate1d(ref, h, axis=ax, mode="reflect")
+    out = oracle.box_filter_3d(vol, b["r"], b["w"], oracle.REFLECT)
+    assert np.max(np.abs(out - ref)) <= 1e-11 * 255
+    const = np.full((6, 7, 8), 77.25)
+    assert np.max(np.abs(oracle.box_filter_3d(const, b["r"], b["w"]) - 77.25)) <= 1e-12
