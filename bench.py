@@ -275,6 +275,48 @@ def strided_workload(steps):
     return {"H": H, "W": W, "sigma": 8.0, "K": 3, "ms_full_filter": round(ms_full, 5), "steps": out}
 
 
+def volume_workload(steps):
+    """A 256 x 256 x 256 FP32 volume (a stack of seeded 1/f slices), sigma
+    in {2, 4}, K = 3, filtered along x, y (slices, one batched launch) and z:
+    time per volume, its HBM fraction on the algorithmic bytes (read once +
+    write once), and the largest error against the FP64 volume oracle."""
+    import torch
+    import oracle
+    import paper_1107_4958_amd as rsg
+    import synthimg
+    D = H = W = 256
+    vol = np.stack([synthimg.image(H, W, 1, "f32", 300 + z) for z in range(D)])
+    srcs = [to_dev(vol, "f32"), None]
+    srcs[1] = srcs[0].clone()
+    dsts = [torch.empty_like(srcs[0]) for _ in srcs]
+    stream = torch.cuda.current_stream()
+    out = []
+    for sigma in (2.0, 4.0):
+        def launch(i):
+            rsg.rsg_gauss_filter_3d(srcs[i % 2].data_ptr(), dsts[i % 2].data_ptr(), D, H, W, 1, rsg.RSG_F32, sigma, 3,
+                                    None, rsg.RSG_REPLICATE, stream.cuda_stream)
+
+        for i in range(3):
+            launch(i)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(steps):
+            launch(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        got = dsts[(steps - 1) % 2].cpu().numpy().astype(np.float64)
+        b = oracle.boxes(sigma, 3)
+        ref = oracle.box_filter_3d(vol.astype(np.float64), b["r"], b["w32"].astype(np.float64))
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        alg = 2.0 * D * H * W * 4
+        out.append({"sigma": sigma, "K": 3, "ms": round(ms, 4), "gvox_s": round(D * H * W / (ms * 1e-3) / 1e9, 2),
+                    "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "parity_max_rel_err": float("%.3g" % err)})
+    return {"D": D, "H": H, "W": W, "runs": out}
+
+
 def sigma_k_grid(imgs, steps):
     """Gpixel/s and HBM fraction at 4096^2 for sigma in {2, 8, 32}, K in {3, 4, 5}."""
     out = []
@@ -550,6 +592,8 @@ def main():
         result["fit_study_1024"] = fit_study()
         print("bench: strided", file=sys.stderr, flush=True)
         result["strided_8192"] = strided_workload(20)
+        print("bench: volume", file=sys.stderr, flush=True)
+        result["volume_256"] = volume_workload(20)
         print("bench: batch", file=sys.stderr, flush=True)
         result["batch"] = batch_workload(5, gpx if args.dtype == "f32" else None)
         print("bench: precision", file=sys.stderr, flush=True)

@@ -153,6 +153,20 @@ int rsg_box_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtyp
 int rsg_gauss_filter_strided(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt, double sigma,
                              int K, const rsg_boxes* boxes, rsg_boundary b, int step, void* stream);
 
+/* Filter a D x H x W x C FP32 volume (slice stride H*W*C, contiguous) with
+ * the same K boxes along x, y and z: the separable method with one more 1D
+ * pass for the third axis (Section 4 notes the extension to d dimensions).
+ * Boxes: `boxes` if not NULL, else rsg_fit_boxes(sigma, K).  The slices are
+ * filtered along x and y in one batched launch into a stream-ordered FP32
+ * intermediate of D*H*W*C words, which a z-pass kernel filters along z into
+ * d_dst (hipMallocAsync / hipFreeAsync on `stream`).  FP32 only: an exact
+ * uint8 form would need G^3 * 255 < 2^64.
+ * Errors: RSG_EINVAL (NULL pointers, D, H, W < 1, C not in 1..4, overlap,
+ * bad sigma / K / boxes / boundary), RSG_EUNSUPPORTED (dt not FP32; boxes
+ * wider than the kernels' limits: along z R <= 311), RSG_ENOMEM, RSG_EDEVICE. */
+int rsg_gauss_filter_3d(const void* d_src, void* d_dst, int D, int H, int W, int C, rsg_dtype dt, double sigma,
+                        int K, const rsg_boxes* boxes, rsg_boundary b, void* stream);
+
 /* One image of a batch; strides in elements (0 means W*C). */
 typedef struct {
     const void* src;

@@ -108,7 +108,7 @@ class rsg_req_stats(ctypes.Structure):
 SYMBOLS = ("rsg_fit_boxes", "rsg_gauss_filter", "rsg_filter_batch_workspace", "rsg_filter_batch",
            "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_plan_shape",
            "rsg_tune_override", "rsg_tune_path", "rsg_fit_boxes_ex", "rsg_box_filter", "rsg_gauss_filter_strided",
-           "rsg_last_error")
+           "rsg_gauss_filter_3d", "rsg_last_error")
 
 
 def _load():
@@ -132,6 +132,7 @@ def _load():
     lib.rsg_fit_boxes_ex.argtypes = [D, I, I, ctypes.POINTER(rsg_boxes)]
     lib.rsg_box_filter.argtypes = [V, V, I, I, I, I, ctypes.POINTER(rsg_boxes), I, V]
     lib.rsg_gauss_filter_strided.argtypes = [V, V, I, I, I, I, D, I, ctypes.POINTER(rsg_boxes), I, I, V]
+    lib.rsg_gauss_filter_3d.argtypes = [V, V, I, I, I, I, I, D, I, ctypes.POINTER(rsg_boxes), I, V]
     lib.rsg_filter_batch_workspace.argtypes = [ctypes.POINTER(rsg_image_desc), I, ctypes.POINTER(S)]
     lib.rsg_filter_batch.argtypes = [ctypes.POINTER(rsg_image_desc), I, V, S, V]
     lib.rsg_server_create.argtypes = [ctypes.POINTER(rsg_server_config), ctypes.POINTER(V)]
@@ -301,6 +302,28 @@ def filter_strided_tensor(src, sigma: float, K: int, step: int, boundary: int = 
         raise ValueError("out must be a contiguous tensor of shape %r" % (shape,))
     rsg_gauss_filter_strided(src.data_ptr(), out.data_ptr(), H, W, C, tensor_dtype_code(src), sigma, K, boxes,
                              boundary, step, _stream_handle(src, stream))
+    return out
+
+
+def rsg_gauss_filter_3d(d_src: int, d_dst: int, D: int, H: int, W: int, C: int, dt: int, sigma: float, K: int,
+                        boxes=None, boundary: int = RSG_REPLICATE, stream: int = 0) -> None:
+    _check(_lib.rsg_gauss_filter_3d(ctypes.c_void_p(d_src), ctypes.c_void_p(d_dst), D, H, W, C, dt, float(sigma),
+                                    int(K), ctypes.byref(boxes) if boxes is not None else None, boundary,
+                                    ctypes.c_void_p(stream)))
+
+
+def filter_volume_tensor(vol, sigma: float, K: int, boundary: int = RSG_REPLICATE, out=None, stream=None,
+                         boxes=None):
+    """Filter a contiguous D x H x W (x C) FP32 device tensor along all three axes."""
+    import torch
+    if not vol.is_cuda or not vol.is_contiguous() or vol.dim() not in (3, 4):
+        raise ValueError("vol must be a contiguous D x H x W (x C) device tensor")
+    D, H, W = vol.shape[:3]
+    C = vol.shape[3] if vol.dim() == 4 else 1
+    if out is None:
+        out = torch.empty_like(vol)
+    rsg_gauss_filter_3d(vol.data_ptr(), out.data_ptr(), D, H, W, C, tensor_dtype_code(vol), sigma, K, boxes,
+                        boundary, _stream_handle(vol, stream))
     return out
 
 

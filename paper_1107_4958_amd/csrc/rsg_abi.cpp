@@ -25,14 +25,15 @@ int set_error(int code, const char* fmt, ...)
 }
 
 // Plans every image and builds the flat work list of a batched launch.
-int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std::vector<BatchTask>& tasks)
+int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std::vector<BatchTask>& tasks,
+               int hs_pref)
 {
     if (!d || n < 1) return set_error(RSG_EINVAL, "batch needs n >= 1 descriptors");
     imgs.resize(n);
     tasks.clear();
     int64_t total = 0;
     for (int i = 0; i < n; ++i) {
-        int rc = plan_image(d[i], &imgs[i]);
+        int rc = plan_image(d[i], &imgs[i], 1, hs_pref);
         if (rc != RSG_OK) {
             std::string msg = g_last_error;
             return set_error(rc, "image %d: %s", i, msg.c_str());

@@ -277,6 +277,7 @@ __device__ __forceinline__ void store_out<TrBF16>(__amdgpu_buffer_rsrc_t rs, int
 struct TaskGeom {
     int s0, y0, hs, a0, off, niter, ybase;
     int emit0;                                 // first iteration that emits a row (a multiple of G)
+    int64_t slice_off;                         // byte offset of the task's slice (stacked images)
 };
 
 // --------------------------------------------------------------------------
@@ -321,9 +322,9 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     const int y_hi = H - 1;
     const int64_t sstride = ip.src_stride * es;
     const int64_t dstride = ip.dst_stride * es;
-    const char* sbase = reinterpret_cast<const char*>(ip.src) + int64_t(y_lo) * sstride;
+    const char* sbase = reinterpret_cast<const char*>(ip.src) + tg.slice_off + int64_t(y_lo) * sstride;
     const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(y_hi - y_lo) * sstride + int64_t(WC) * es);
-    const char* dbase = reinterpret_cast<const char*>(ip.dst) + int64_t(tg.y0) * dstride;
+    const char* dbase = reinterpret_cast<const char*>(ip.dst) + tg.slice_off + int64_t(tg.y0) * dstride;
     const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(dbase, int64_t(tg.hs - 1) * dstride + int64_t(WC) * es);
     const int s = tg.s0 + lane;                // this lane's column
     // Output row k of the task is stored at ocol + k * dstride: lanes past the
@@ -664,7 +665,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
         const int jrow = lane / SEG;
         const int q = lane % SEG;
         const int y_lo = max(0, tg.ybase);
-        const char* sbase = reinterpret_cast<const char*>(ip.src) + int64_t(y_lo) * sstride;
+        const char* sbase = reinterpret_cast<const char*>(ip.src) + tg.slice_off + int64_t(y_lo) * sstride;
         const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(H - 1 - y_lo) * sstride + int64_t(WC) * es);
         const int cs = tg.a0 + NPL * q;
         const int vec_voff = cs * es;
@@ -780,7 +781,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
         }
     } else {
         // ---------------- column pass ----------------
-        const char* dbase = reinterpret_cast<char*>(ip.dst) + int64_t(tg.y0) * dstride;
+        const char* dbase = reinterpret_cast<char*>(ip.dst) + tg.slice_off + int64_t(tg.y0) * dstride;
         const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(dbase, int64_t(tg.hs - 1) * dstride + int64_t(WC) * es);
         const int s = tg.s0 + lane;
         const uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
@@ -847,6 +848,13 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
 {
     constexpr int G = kWave / SEG;
     TaskGeom tg;
+    tg.slice_off = 0;
+    if (ip.nslices > 1) {                      // a stack of equal images: slice-major task order
+        const int per = ip.nstrips * ip.nsegs;
+        const int slice = task / per;
+        task -= slice * per;
+        tg.slice_off = int64_t(slice) * ip.slice_stride * Tr::kSize;
+    }
     const int strip = task % ip.nstrips;
     const int seg = task / ip.nstrips;
     const int pre = (G - (2 * ip.R + 1) % G) % G;

@@ -8,6 +8,8 @@
 
 #include "rsg.h"
 
+#include <vector>
+
 namespace rsg {
 
 // Records the message for rsg_last_error() on this thread; returns `code`.
@@ -62,6 +64,8 @@ struct ImgParams {
     // two-pass path (wide boxes): row filter + transposed store, twice
     int32_t path;                  // kPathFused or kPathTwoPass
     int32_t step;                  // output stride in pixels along both axes (1: every pixel; two-pass only)
+    int32_t nslices;               // fused path: a stack of this many equal images (<= 1: one image)
+    int64_t slice_stride;          // elements from one image of the stack to the next (source and destination)
     int32_t pc;                    // fused path: 1 = producer / consumer workgroups of two waves
     int32_t pnpl[2];               // samples per lane of pass A, pass B
     int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
@@ -74,6 +78,24 @@ constexpr int kPathTwoPass = 1;
 // One pass of the two-pass path: filter `rows` rows of `len` samples (taps C
 // samples apart) and store the result transposed (element (x, row) at
 // dst[x * dst_stride + row]).
+// The pass along z of an FP32 volume (D slices of `plane` samples).
+struct ZParams {
+    const float* src;
+    float* dst;
+    int64_t plane;                 // samples per slice (H W C)
+    int32_t D, R;
+    int32_t hz;                    // output slices per task
+    int32_t ncols;                 // 64-sample columns per slice
+    int32_t ntasks;                // ncols x segments
+    int32_t L;                     // ring length 2R + 2
+    int32_t boundary;
+    int32_t r[RSG_MAX_K];
+    float wf[RSG_MAX_K];
+    float dc32;
+};
+// Launches the z pass with `wpb` waves (tasks) per workgroup.
+int launch_zpass_f32(const ZParams& zp, int kt, int wpb, hipStream_t stream);
+
 struct PassParams {
     const void* src;
     void* dst;
@@ -103,7 +125,9 @@ struct BatchTask {
 };
 
 // Plan for one image: validates, fits (cached), picks the tile shape.
-int plan_image(const rsg_image_desc& d, ImgParams* ip, int step = 1);   // step > 1: strided output, two-pass
+// step > 1: strided output (two-pass path); hs_pref > 0: segment height of a
+// fused plan chosen by the caller (volumes), instead of the table or rule
+int plan_image(const rsg_image_desc& d, ImgParams* ip, int step = 1, int hs_pref = 0);
 // Process-wide segment height that overrides the tuning table (0: none).
 void set_hs_override(int hs);
 // Process-wide path override (0: planner's choice, 1: fused, 2: two-pass).
@@ -138,6 +162,9 @@ int launch_pass_batch_f16(const PassBatchLaunch& b, hipStream_t stream);
 int launch_pass_batch_bf16(const PassBatchLaunch& b, hipStream_t stream);
 // Row blocks of the two-pass images of a batch (both passes).
 int64_t pass_blocks(const ImgParams* imgs, int nimg);
+// Plans every image and builds the flat work list of a batched launch.
+int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std::vector<BatchTask>& tasks,
+               int hs_pref = 0);
 // Window geometry of one pass (shared by the planner and the launcher).
 constexpr int kPassRowsHost = 16;
 inline int pass_win_pitch(int npl, int hw) { return (kWave * npl + hw + 3 + 3) / 4 * 4; }

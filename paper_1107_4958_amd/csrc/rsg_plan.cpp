@@ -133,7 +133,7 @@ int check_boxes(const rsg_boxes& b, bool need_u8)
 void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_order_relaxed); }
 void set_path_override(int path) { g_path_override.store(path, std::memory_order_relaxed); }
 
-int plan_image(const rsg_image_desc& d, ImgParams* ip, int step)
+int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
 {
     if (step < 1) return set_error(RSG_EINVAL, "output step must be >= 1 (got %d)", step);
     if (!d.src || !d.dst) return set_error(RSG_EINVAL, "NULL image pointer");
@@ -285,7 +285,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step)
     p.nstrips = int((WC + kWave - 1) / kWave);
 
     // ---- segment height ----
-    int hs = (tabled && hs_t > 0) ? hs_t : default_hs(d.H, p.nstrips, R, p.lds_bytes);
+    int hs = hs_pref > 0 ? hs_pref : ((tabled && hs_t > 0) ? hs_t : default_hs(d.H, p.nstrips, R, p.lds_bytes));
     hs = std::max(1, std::min(hs, d.H));
     {   // every offset a task touches (rows ybase .. ybase + its padded
         // iteration count, times the larger stride) must stay below 2^30

@@ -23,7 +23,6 @@
 #include <vector>
 
 namespace rsg {
-int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std::vector<BatchTask>& tasks);
 
 namespace {
 

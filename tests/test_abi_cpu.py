@@ -21,7 +21,7 @@ def _rsg():
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "rsg.h")).read()
     declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(rsg_\w+)\s*\(", header, re.M))
-    assert len(declared) == 15
+    assert len(declared) == 16
     rsg = _rsg()
     lib = ctypes.CDLL(rsg.LIB_PATH)
     for name in declared:
@@ -227,3 +227,15 @@ def test_strided_validation():
     assert lib.rsg_gauss_filter_strided(A, B, 64, 64, 1, rsg.RSG_F32, 2.0, 3, None, 0, 0, None) == rsg.RSG_EINVAL
     assert lib.rsg_gauss_filter_strided(A, B, 64, 64, 4, rsg.RSG_F32, 60.0, 5, None, 0, 2, None) == rsg.RSG_EUNSUPPORTED
     assert lib.rsg_gauss_filter_strided(None, B, 64, 64, 1, rsg.RSG_F32, 2.0, 3, None, 0, 2, None) == rsg.RSG_EINVAL
+
+
+def test_volume_validation():
+    """Refusals of the volume entry point happen on the host, before any allocation or launch."""
+    rsg = _rsg()
+    lib = rsg.lib()
+    A, B = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x90000000)
+    assert lib.rsg_gauss_filter_3d(A, B, 4, 8, 8, 1, rsg.RSG_U8, 2.0, 3, None, 0, None) == rsg.RSG_EUNSUPPORTED
+    assert lib.rsg_gauss_filter_3d(A, B, 0, 8, 8, 1, rsg.RSG_F32, 2.0, 3, None, 0, None) == rsg.RSG_EINVAL
+    assert lib.rsg_gauss_filter_3d(A, B, 4, 8, 8, 5, rsg.RSG_F32, 2.0, 3, None, 0, None) == rsg.RSG_EINVAL
+    assert lib.rsg_gauss_filter_3d(A, ctypes.c_void_p(0x100000 + 64), 4, 8, 8, 1, rsg.RSG_F32, 2.0, 3, None, 0,
+                                   None) == rsg.RSG_EINVAL

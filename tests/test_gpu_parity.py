@@ -325,3 +325,46 @@ def test_strided_at_scale_4096(dtype, step):
         ref = oracle.box_filter_points(img3.astype(np.float64), b["r"], b["w32"].astype(np.float64),
                                        ys * step, xs * step, cs)
         assert float(np.max(np.abs(out[ys, xs] - ref))) / float(np.max(np.abs(img))) <= FP32_TOL
+
+
+# --------------------------------------------------------------------------
+# Volumes: x, y per slice, then z
+# --------------------------------------------------------------------------
+VOLUMES = [(1, 1, 1, 1), (5, 7, 9, 1), (17, 33, 20, 2), (40, 64, 65, 3), (9, 3, 300, 4), (130, 17, 19, 1)]
+
+
+def _volume_gpu(vol, sigma, K, boundary, boxes=None):
+    import torch
+    import paper_1107_4958_amd as rsg
+    src = torch.from_numpy(np.ascontiguousarray(vol, dtype=np.float32)).cuda()
+    out = rsg.filter_volume_tensor(src, sigma, K, boundary, boxes=boxes)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("D,H,W,C", VOLUMES)
+@pytest.mark.parametrize("boundary", [oracle.REPLICATE, oracle.ZERO, oracle.REFLECT])
+@pytest.mark.parametrize("sigma,K", [(1.5, 3), (4.0, 5), (12.0, 4)])
+def test_volume_parity(D, H, W, C, boundary, sigma, K):
+    rng = np.random.default_rng(D * 7 + H * 3 + W + C)
+    vol = rng.uniform(0, 255, size=(D, H, W, C) if C > 1 else (D, H, W)).astype(np.float32)
+    b = oracle.boxes(sigma, K)
+    out = _volume_gpu(vol, sigma, K, boundary)
+    ref = oracle.box_filter_3d(vol.astype(np.float64), b["r"], b["w32"].astype(np.float64), boundary)
+    assert rel_max_err(out, ref) <= FP32_TOL
+
+
+def test_volume_at_size_and_direct_boxes():
+    """A 96 x 160 x 200 one-over-f stack, every voxel; and the direct fit at
+    small sigma passed as boxes."""
+    import paper_1107_4958_amd as rsg
+    vol = np.stack([synthimg.image(160, 200, 1, "f32", 70 + z) for z in range(96)])
+    b = oracle.boxes(3.0, 3)
+    out = _volume_gpu(vol, 3.0, 3, oracle.REPLICATE)
+    ref = oracle.box_filter_3d(vol.astype(np.float64), b["r"], b["w32"].astype(np.float64))
+    assert rel_max_err(out, ref) <= FP32_TOL
+    bd = rsg.rsg_fit_boxes_ex(0.9, 3, rsg.RSG_FIT_DIRECT)
+    o = oracle.boxes_direct(0.9, 3)
+    out = _volume_gpu(vol[:20], 0.0, 0, oracle.REFLECT, boxes=bd)
+    ref = oracle.box_filter_3d(vol[:20].astype(np.float64), o["r"], o["w32"].astype(np.float64), oracle.REFLECT)
+    assert rel_max_err(out, ref) <= FP32_TOL
