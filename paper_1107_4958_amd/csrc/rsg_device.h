@@ -480,17 +480,18 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     };
 
     // Column pass, first half: running sums down the columns (Eq. alg1) of
-    // the queued group into the ring.  Float types enter each row as
-    // (T + off * dc) - c2, folded into the row combine: the offset restores
-    // the row's true box sums, c2 keeps the column sums small.  (The
-    // two-wave form computes exactly the same values, so batched and single
-    // launches agree bit for bit.)
+    // the queued group into the ring.  Float rows arrive as T + off * dc
+    // (the group offset restores the row's true box sums, folded into the
+    // row combine) and enter the sums as (T + off * dc) - c2: c2, the task's
+    // first row, keeps the column sums small.  (The multi-wave form computes
+    // exactly the same values, so every form agrees bit for bit.)
     auto col_push = [&]() {
         const int wbase = slot0 * RP + lane;
         const int mbase = (slot0 == 0 ? L : slot0) * RP + lane;
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            colacc += Tq[j];
+            if constexpr (kInt) colacc += Tq[j];
+            else colacc += Tq[j] - c2;
             ring[wbase + j * RP] = colacc;
             ring[mbase + j * RP] = colacc;          // mirror copy (same slot unless slot0 == 0)
         }
@@ -567,13 +568,11 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         const float off_next = row_scan(1, buf[1 % PF], 1);
         Acc T[G];
         float init = 0.0f;
-        if constexpr (!kInt) init = off_cur * dc - c2;     // c2 = 0 here: the first row's true value
+        if constexpr (!kInt) init = off_cur * dc;
         row_combine(pv, T, init);
         if constexpr (!kInt) {
-            c2 = T[0];
+            c2 = T[0];                                  // the column offset: the task's first row
             c2dc = c2 * dc;
-#pragma unroll
-            for (int j = 0; j < G; ++j) T[j] -= c2;
         }
         dropped_stores(PF * G + G);
 #pragma unroll
@@ -591,7 +590,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
             const int gg = g + b;
             const float off_next = row_scan(gg + 1, buf[(2 + b) % PF], b & 1);
             float init = 0.0f;
-            if constexpr (!kInt) init = off_cur * dc - c2;
+            if constexpr (!kInt) init = off_cur * dc;
             Acc T[G];
             row_combine(pv, T, init);
             col_combine(gg - 1, rv);
@@ -610,15 +609,18 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 
 // --------------------------------------------------------------------------
 // Producer / consumer form of the streaming loop: one task per workgroup of
-// two waves.  Wave 0 runs the row pass of every group (loads, running sums,
-// row box differences) and hands the group's row results to wave 1 through a
-// two-slot LDS queue; wave 1 runs the column pass (running column sums in the
-// ring, column box differences, stores).  One workgroup barrier per group
-// passes a queue slot: at barrier g slot g & 1 holds group g, and the slot
-// wave 0 fills next was read by wave 1 before it reached barrier g.  Both
-// waves take the same number of barriers.  The split doubles the waves per
-// task without adding halo rows, and each wave's chain of dependent LDS round
-// trips is half as long.
+// kProducers + 1 waves.  The row pass is independent from row to row, so
+// waves 0 .. NPR-1 each run it for every NPR-th group (loads, running sums,
+// row box differences) and hand the group's row results to the last wave
+// through an LDS queue; that wave runs the column pass of the groups in
+// order (running column sums in the ring, column box differences, stores).
+// Step s covers groups s NPR .. s NPR + NPR - 1 and ends, for the row-pass
+// waves, in one workgroup barrier: at barrier s queue slot s & 1 holds the
+// step's groups, and the slot the row-pass waves fill next was read by the
+// column-pass wave before it reached barrier s.  Every wave takes the same
+// number of barriers.  The split multiplies the waves per task without
+// adding halo rows, and each wave's chain of dependent LDS round trips is a
+// fraction of the one-wave form's.
 // --------------------------------------------------------------------------
 template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE>
 __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
@@ -641,14 +643,15 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
     const int boundary = ip.boundary;
     static_assert(PW <= PP, "tile pitch");
 
-    // LDS: [row tile G x PP][queue 2 x G x 64][column offsets 64][ring (L + G) x 64]
+    constexpr int NPR = kProducers;
+    // LDS: [row tiles NPR x G x PP][queue 2 x NPR x G x 64][ring (L + G) x 64]
     Acc* P = reinterpret_cast<Acc*>(lds);
-    Acc* Q = P + G * PP;
-    float* c2s = reinterpret_cast<float*>(Q + 2 * G * kWave);
-    Acc* ring = reinterpret_cast<Acc*>(c2s + kWave);
+    Acc* Q = P + NPR * G * PP;
+    Acc* ring = Q + 2 * NPR * G * kWave;
 
     const int ngroups = (tg.niter + G - 1) / G;
-    const int nsteps = (ngroups + PF - 1) / PF * PF;    // both waves: one barrier per step
+    // steps of NPR groups, a multiple of PF; every wave: one barrier per step
+    const int nsteps = (ngroups + NPR * PF - 1) / (NPR * PF) * PF;
     const float dc = ip.dc32;
     float wf[KT];
     uint32_t wm[KT];
@@ -660,8 +663,9 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
     const int64_t sstride = ip.src_stride * es;
     const int64_t dstride = ip.dst_stride * es;
 
-    if (wave == 0) {
-        // ---------------- row pass ----------------
+    if (wave < NPR) {
+        // ---------------- row pass of groups wave, wave + NPR, ... ----------------
+        Acc* Pt = P + wave * G * PP;
         const int jrow = lane / SEG;
         const int q = lane % SEG;
         const int y_lo = max(0, tg.ybase);
@@ -680,8 +684,8 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
             }
         }
         const int sstride32 = int(sstride);
-        auto load = [&](Chunk<Tr, NPL>& ch, int g) {
-            const int y = tg.ybase + g * G + jrow;
+        auto load = [&](Chunk<Tr, NPL>& ch, int st) {    // the group of step st
+            const int y = tg.ybase + (st * NPR + wave) * G + jrow;
             const int ye = ext_index(y, H, boundary);
             const bool zero_row = ye < 0;
             const int rowoff = (zero_row ? 0 : ye - y_lo) * sstride32;
@@ -707,7 +711,6 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
             load(buf[b], b);
         }
         __builtin_amdgcn_sched_barrier(0);
-        float c2 = 0.0f;
         for (int g = 0; g < nsteps; g += PF) {
 #pragma unroll
             for (int b = 0; b < PF; ++b) {
@@ -737,7 +740,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
                     for (int i = c; i < NPL; i += C) v[i] = v[i] + ex;
                 }
                 using Acc4 = typename std::conditional<kInt, uint4, float4>::type;
-                Acc4* dst4 = reinterpret_cast<Acc4*>(P + jrow * PP + q * NPL);
+                Acc4* dst4 = reinterpret_cast<Acc4*>(Pt + jrow * PP + q * NPL);
 #pragma unroll
                 for (int h = 0; h < NPL / 4; ++h) {
                     Acc4 t4;
@@ -746,13 +749,13 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
                 }
                 wave_lds_fence();
                 // row box differences (Eq. indep), lane = column; floats add
-                // the group offset's share and subtract the column offset c2
+                // the group offset's share
                 float init = 0.0f;
-                if constexpr (!kInt) init = off * dc - c2;
+                if constexpr (!kInt) init = off * dc;
                 Acc T[G];
 #pragma unroll
                 for (int j = 0; j < G; ++j) {
-                    const Acc* Pj = P + j * PP;
+                    const Acc* Pj = Pt + j * PP;
                     Acc t;
                     if constexpr (kInt) {
                         t = 0;
@@ -765,15 +768,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
                     }
                     T[j] = t;
                 }
-                if constexpr (!kInt) {
-                    if (gg == 0) {                   // column offset: the first row's true value
-                        c2 = T[0];
-#pragma unroll
-                        for (int j = 0; j < G; ++j) T[j] -= c2;
-                        c2s[lane] = c2;
-                    }
-                }
-                Acc* Qs = Q + (gg & 1) * G * kWave;
+                Acc* Qs = Q + ((gg & 1) * NPR + wave) * G * kWave;
 #pragma unroll
                 for (int j = 0; j < G; ++j) Qs[j * kWave + lane] = T[j];
                 __syncthreads();
@@ -787,19 +782,27 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
         const uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
         const uint32_t dstr = uint32_t(dstride);
         Acc colacc = Acc(0);
+        float c2 = 0.0f;
         float c2dc = 0.0f;
         int slot0 = 0;
-        for (int g = 0; g < nsteps; ++g) {
+        for (int st = 0; st < nsteps; ++st) {
             __syncthreads();
+#pragma unroll 1
+          for (int pq = 0; pq < NPR; ++pq) {
+            const int g = st * NPR + pq;
+            const Acc* Qs = Q + ((st & 1) * NPR + pq) * G * kWave;
             if constexpr (!kInt) {
-                if (g == 0) c2dc = c2s[lane] * dc;
+                if (g == 0) {                    // the column offset: the task's first row
+                    c2 = Qs[lane];
+                    c2dc = c2 * dc;
+                }
             }
-            const Acc* Qs = Q + (g & 1) * G * kWave;
             const int wbase = slot0 * RP + lane;
             const int mbase = (slot0 == 0 ? L : slot0) * RP + lane;
 #pragma unroll
             for (int j = 0; j < G; ++j) {
-                colacc += Qs[j * kWave + lane];
+                if constexpr (kInt) colacc += Qs[j * kWave + lane];
+                else colacc += Qs[j * kWave + lane] - c2;
                 ring[wbase + j * RP] = colacc;
                 ring[mbase + j * RP] = colacc;
             }
@@ -838,6 +841,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
             }
             slot0 += G;
             slot0 -= (slot0 >= L) ? L : 0;
+          }
         }
     }
 }
@@ -891,7 +895,7 @@ __device__ __forceinline__ int xcd_task(int b, int n)
 
 // One task per workgroup of two waves (row-pass and column-pass waves).
 template <class Tr, int C, int SEG, int NPL, int KT>
-__global__ __launch_bounds__(2 * kWave) void k_single_pc(ImgParams ip)
+__global__ __launch_bounds__((kProducers + 1) * kWave) void k_single_pc(ImgParams ip)
 {
     extern __shared__ uint32_t lds[];
     run_task<Tr, C, SEG, NPL, KT, true>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
@@ -932,7 +936,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // items and runs them as a row-pass / column-pass pair.  LDS word 0 carries
 // the popped index to both waves; the task's LDS starts 16 bytes later.
 template <class Tr, int C, int KT, int S0, int N0, int S1, int N1, int S2, int N2, int S3, int N3>
-__global__ __launch_bounds__(2 * kWave) void k_batch_pc(const ImgParams* __restrict__ imgs,
+__global__ __launch_bounds__((kProducers + 1) * kWave) void k_batch_pc(const ImgParams* __restrict__ imgs,
                                                        const BatchTask* __restrict__ tasks, int ntasks,
                                                        unsigned* __restrict__ counter)
 {

@@ -31,7 +31,7 @@ int launch_one(const ImgParams& ip, hipStream_t st)
         auto fn = dev::k_single_pc<Tr, C, SEG, NPL, KT>;
         int rc = set_lds_limit(reinterpret_cast<const void*>(fn), ip.lds_bytes);
         if (rc != RSG_OK) return rc;
-        hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3(2 * kWave), ip.lds_bytes, st, ip);
+        hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3((kProducers + 1) * kWave), ip.lds_bytes, st, ip);
         return RSG_OK;
     }
     auto fn = dev::k_single<Tr, C, SEG, NPL, KT>;
@@ -89,7 +89,8 @@ int batch_one(const BatchClassLaunch& b, hipStream_t st)
                                   Lo::N[3]>;
         int rc = set_lds_limit(reinterpret_cast<const void*>(fn), b.lds);
         if (rc != RSG_OK) return rc;
-        hipLaunchKernelGGL(fn, dim3(b.grid), dim3(2 * kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks, b.d_counter);
+        hipLaunchKernelGGL(fn, dim3(b.grid), dim3((kProducers + 1) * kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks,
+                           b.d_counter);
         return RSG_OK;
     }
     auto fn = dev::k_batch<Tr, C, KT, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2], Lo::N[2], Lo::S[3], Lo::N[3]>;

@@ -27,6 +27,10 @@ constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies
 #define RSG_PREFETCH 2
 #endif
 constexpr int kPrefetch = RSG_PREFETCH;   // groups of row loads in flight per wave
+#ifndef RSG_PRODUCERS
+#define RSG_PRODUCERS 1
+#endif
+constexpr int kProducers = RSG_PRODUCERS;   // row-pass waves per task of the multi-wave fused form
 constexpr int64_t kOffsetLimit = int64_t(1) << 30;   // every byte offset a task touches stays below this
 
 // Everything one image's kernel needs; plain data, copied to the device for
@@ -205,12 +209,12 @@ inline void scan_layout(int C, int i, int* seg, int* npl)
 // 32 (mod 64) words puts the pair in opposite halves of the 64 banks.  The
 // column ring keeps the dense 64-word pitch (one word per lane).
 constexpr int row_tile_pitch(int seg, int npl) { return seg * npl + 32; }
-// Producer / consumer form: one row tile, a two-slot queue of G rows, the
-// column offsets and the ring of L + G rows.
+// Producer / consumer form: one row tile per row-pass wave, a two-slot
+// queue of kProducers groups of G rows, and the ring of L + G rows.
 inline uint32_t tile_lds_bytes_pc(int seg, int npl, int L)
 {
     const int G = kWave / seg;
-    return uint32_t(4 * (G * row_tile_pitch(seg, npl) + 2 * G * kWave + kWave + (L + G) * kWave));
+    return uint32_t(4 * (kProducers * G * row_tile_pitch(seg, npl) + 2 * kProducers * G * kWave + (L + G) * kWave));
 }
 // Two row tiles (double-buffered) and the ring of L + G rows.
 inline uint32_t tile_lds_bytes(int seg, int npl, int L)

@@ -279,9 +279,11 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     p.pc = (ov == 3) ? 0 : 1;
     p.lds_one = tile_lds_bytes(seg, npl, p.L);
     p.lds_bytes = p.pc ? tile_lds_bytes_pc(seg, npl, p.L) : p.lds_one;
-    if (std::max(p.lds_bytes, p.lds_one) > kLdsLimit)
-        return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", std::max(p.lds_bytes, p.lds_one),
-                         kLdsLimit);
+    {   // the batch kernel of the multi-wave form adds its task slot
+        const uint32_t need = std::max(p.lds_bytes + (p.pc ? 4u * kBatchSlotWords : 0u), p.lds_one);
+        if (need > kLdsLimit)
+            return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", need, kLdsLimit);
+    }
     p.nstrips = int((WC + kWave - 1) / kWave);
 
     // ---- segment height ----
@@ -291,7 +293,9 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         // iteration count, times the larger stride) must stay below 2^30
         const int64_t stride_b = std::max(ss, ds) * es;
         auto fits = [&](int h) {
-            const int64_t rows = int64_t(h) + 2 * R + 1 + (p.G - 1) + int64_t(kPrefetch + 1) * p.G;
+            // (the multi-wave form pads to whole steps of kProducers groups
+            // and prefetches kPrefetch steps ahead)
+            const int64_t rows = int64_t(h) + 2 * R + 1 + (p.G - 1) + int64_t(kProducers) * (2 * kPrefetch + 1) * p.G;
             return rows * stride_b + WC * es <= kOffsetLimit;
         };
         while (hs > 1 && !fits(hs)) hs = (hs + 1) / 2;
