@@ -135,32 +135,43 @@ template <> struct PassOutOf<dev::TrF32> { static constexpr int v = dev::kOutF32
 template <> struct PassOutOf<dev::TrF16> { static constexpr int v = dev::kOutF16; };
 template <> struct PassOutOf<dev::TrBF16> { static constexpr int v = dev::kOutBF16; };
 
-// A pass launch: one image (pb == nullptr) or a batch class.
-template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
+// A pass launch: one image (pb == nullptr) or a batch class; TR rows per workgroup.
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST, int TR>
 int pass_one(const PassParams* pp, const PassBatchLaunch* pb, uint32_t lds, hipStream_t st)
 {
     if (pb) {
-        auto fn = dev::k_pass_batch<TrIn, OUT, C, NPL, KT, ST>;
+        auto fn = dev::k_pass_batch<TrIn, OUT, C, NPL, KT, ST, TR>;
         int rc = set_lds_limit(reinterpret_cast<const void*>(fn), lds);
         if (rc != RSG_OK) return rc;
-        hipLaunchKernelGGL(fn, dim3(pb->ntasks), dim3(dev::kPassRows * kWave), lds, st, pb->d_pps, pb->d_tasks);
+        hipLaunchKernelGGL(fn, dim3(pb->ntasks), dim3(TR * kWave), lds, st, pb->d_pps, pb->d_tasks);
         return RSG_OK;
     }
-    auto fn = dev::k_pass<TrIn, OUT, C, NPL, KT, ST>;
+    auto fn = dev::k_pass<TrIn, OUT, C, NPL, KT, ST, TR>;
     int rc = set_lds_limit(reinterpret_cast<const void*>(fn), lds);
     if (rc != RSG_OK) return rc;
-    const int grid = (pp->rows + dev::kPassRows - 1) / dev::kPassRows;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(dev::kPassRows * kWave), lds, st, *pp);
+    const int grid = (pp->rows + TR - 1) / TR;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(TR * kWave), lds, st, *pp);
     return RSG_OK;
 }
 
+// 8-row workgroups exist for the wide multi-channel windows of pass A only (C >= 2)
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
+int pass_tr(int tr, const PassParams* pp, const PassBatchLaunch* pb, uint32_t lds, hipStream_t st)
+{
+    if (tr == dev::kPassRows) return pass_one<TrIn, OUT, C, NPL, KT, ST, dev::kPassRows>(pp, pb, lds, st);
+    if constexpr (C >= 2) {
+        if (tr == 8) return pass_one<TrIn, OUT, C, NPL, KT, ST, 8>(pp, pb, lds, st);
+    }
+    return set_error(RSG_EUNSUPPORTED, "no pass kernel with %d rows per workgroup for C=%d", tr, C);
+}
+
 template <class TrIn, int OUT, int C, int NPL, int ST>
-int pass_k(int kt, const PassParams* pp, const PassBatchLaunch* pb, uint32_t lds, hipStream_t st)
+int pass_k(int kt, int tr, const PassParams* pp, const PassBatchLaunch* pb, uint32_t lds, hipStream_t st)
 {
     switch (kt) {
-    case 3: return pass_one<TrIn, OUT, C, NPL, 3, ST>(pp, pb, lds, st);
-    case 4: return pass_one<TrIn, OUT, C, NPL, 4, ST>(pp, pb, lds, st);
-    case 5: return pass_one<TrIn, OUT, C, NPL, 5, ST>(pp, pb, lds, st);
+    case 3: return pass_tr<TrIn, OUT, C, NPL, 3, ST>(tr, pp, pb, lds, st);
+    case 4: return pass_tr<TrIn, OUT, C, NPL, 4, ST>(tr, pp, pb, lds, st);
+    case 5: return pass_tr<TrIn, OUT, C, NPL, 5, ST>(tr, pp, pb, lds, st);
     default: return set_error(RSG_EUNSUPPORTED, "no pass kernel for %d taps", kt);
     }
 }
@@ -168,41 +179,41 @@ int pass_k(int kt, const PassParams* pp, const PassBatchLaunch* pb, uint32_t lds
 // samples per lane: 8 or 16 (24 / 12 for three channels: whole pixels);
 // one or two staging tiles
 template <class TrIn, int OUT, int C>
-int pass_npl(int npl, int stages, int kt, const PassParams* pp, const PassBatchLaunch* pb, uint32_t lds,
+int pass_npl(int npl, int stages, int kt, int tr, const PassParams* pp, const PassBatchLaunch* pb, uint32_t lds,
              hipStream_t st)
 {
     constexpr int N0 = (C == 3) ? 12 : 8;
     constexpr int N1 = 2 * N0;
-    if (npl == N0) return stages == 2 ? pass_k<TrIn, OUT, C, N0, 2>(kt, pp, pb, lds, st)
-                                      : pass_k<TrIn, OUT, C, N0, 1>(kt, pp, pb, lds, st);
-    if (npl == N1) return stages == 2 ? pass_k<TrIn, OUT, C, N1, 2>(kt, pp, pb, lds, st)
-                                      : pass_k<TrIn, OUT, C, N1, 1>(kt, pp, pb, lds, st);
+    if (npl == N0) return stages == 2 ? pass_k<TrIn, OUT, C, N0, 2>(kt, tr, pp, pb, lds, st)
+                                      : pass_k<TrIn, OUT, C, N0, 1>(kt, tr, pp, pb, lds, st);
+    if (npl == N1) return stages == 2 ? pass_k<TrIn, OUT, C, N1, 2>(kt, tr, pp, pb, lds, st)
+                                      : pass_k<TrIn, OUT, C, N1, 1>(kt, tr, pp, pb, lds, st);
     return set_error(RSG_EUNSUPPORTED, "no pass kernel for %d samples per lane", npl);
 }
 
 // pass 0 (A: image -> intermediate) or 1 (B: intermediate -> image)
 template <class Tr>
-int pass_any(int pass, int C, int npl, int stages, int kt, const PassParams* pp, const PassBatchLaunch* pb,
+int pass_any(int pass, int C, int npl, int stages, int kt, int tr, const PassParams* pp, const PassBatchLaunch* pb,
              uint32_t lds, hipStream_t st)
 {
     if (pass == 0) {
         constexpr int OUT = Tr::kInt ? dev::kOutMidU32 : dev::kOutMidF32;
         switch (C) {
-        case 1: return pass_npl<Tr, OUT, 1>(npl, stages, kt, pp, pb, lds, st);
-        case 2: return pass_npl<Tr, OUT, 2>(npl, stages, kt, pp, pb, lds, st);
-        case 3: return pass_npl<Tr, OUT, 3>(npl, stages, kt, pp, pb, lds, st);
-        case 4: return pass_npl<Tr, OUT, 4>(npl, stages, kt, pp, pb, lds, st);
+        case 1: return pass_npl<Tr, OUT, 1>(npl, stages, kt, tr, pp, pb, lds, st);
+        case 2: return pass_npl<Tr, OUT, 2>(npl, stages, kt, tr, pp, pb, lds, st);
+        case 3: return pass_npl<Tr, OUT, 3>(npl, stages, kt, tr, pp, pb, lds, st);
+        case 4: return pass_npl<Tr, OUT, 4>(npl, stages, kt, tr, pp, pb, lds, st);
         default: return set_error(RSG_EINVAL, "bad channel count %d", C);
         }
     }
     using Mid = typename std::conditional<Tr::kInt, dev::TrU32, dev::TrF32>::type;
-    return pass_npl<Mid, PassOutOf<Tr>::v, 1>(npl, stages, kt, pp, pb, lds, st);
+    return pass_npl<Mid, PassOutOf<Tr>::v, 1>(npl, stages, kt, tr, pp, pb, lds, st);
 }
 
 template <class Tr>
 int launch_pass_batch_t(const PassBatchLaunch& b, hipStream_t st)
 {
-    int rc = pass_any<Tr>(b.pass, b.C, b.npl, b.stages, b.kt, nullptr, &b, b.lds, st);
+    int rc = pass_any<Tr>(b.pass, b.C, b.npl, b.stages, b.kt, b.tr, nullptr, &b, b.lds, st);
     if (rc != RSG_OK) return rc;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(RSG_EDEVICE, "pass launch failed: %s", hipGetErrorString(e));
@@ -212,7 +223,8 @@ int launch_pass_batch_t(const PassBatchLaunch& b, hipStream_t st)
 template <class Tr>
 int launch_pass_t(const ImgParams& ip, int pass, const PassParams& pp, hipStream_t st)
 {
-    int rc = pass_any<Tr>(pass, ip.C, ip.pnpl[pass], ip.pst[pass], ip.kt, &pp, nullptr, ip.plds[pass], st);
+    int rc = pass_any<Tr>(pass, ip.C, ip.pnpl[pass], ip.pst[pass], ip.kt, ip.ptr[pass], &pp, nullptr, ip.plds[pass],
+                          st);
     if (rc != RSG_OK) return rc;
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(RSG_EDEVICE, "pass launch failed: %s", hipGetErrorString(e));

@@ -74,6 +74,7 @@ struct ImgParams {
     int32_t pnpl[2];               // samples per lane of pass A, pass B
     int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
     uint32_t plds[2];              // LDS bytes per workgroup of pass A, pass B
+    int32_t ptr[2];                // rows (waves) per workgroup of pass A, pass B (16, or 8 for wide windows)
 };
 
 constexpr int kPathFused = 0;
@@ -153,7 +154,7 @@ int launch_pass_bf16(const ImgParams& ip, int pass, const PassParams& pp, hipStr
 // kernel instantiation: workgroup b takes (pass parameters, row block) =
 // d_tasks[b].
 struct PassBatchLaunch {
-    int dtype, pass, C, npl, kt, stages;
+    int dtype, pass, C, npl, kt, stages, tr;
     uint32_t lds;
     const PassParams* d_pps;
     const int2* d_tasks;
@@ -172,10 +173,11 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
 // Window geometry of one pass (shared by the planner and the launcher).
 constexpr int kPassRowsHost = 16;
 inline int pass_win_pitch(int npl, int hw) { return (kWave * npl + hw + 3 + 3) / 4 * 4; }
-// stages: staging tiles (2 lets the stores of chunk k overlap chunk k + 1)
-inline uint32_t pass_lds_bytes(int npl, int hw, int stages)
+// tr: rows (waves) per workgroup; stages: staging tiles (2 lets the stores
+// of chunk k overlap chunk k + 1)
+inline uint32_t pass_lds_bytes(int npl, int hw, int stages, int tr = kPassRowsHost)
 {
-    return uint32_t(4 * (kPassRowsHost * pass_win_pitch(npl, hw) + stages * kWave * npl * (kPassRowsHost + 1)));
+    return uint32_t(4 * (tr * pass_win_pitch(npl, hw) + stages * kWave * npl * (tr + 1)));
 }
 // One persistent launch over the tasks of one (dtype, C, kt) class.
 struct BatchClassLaunch {

@@ -168,7 +168,7 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
     if (!two.empty() && hipMallocAsync(&mid, mid_bytes, stream) != hipSuccess)
         return set_error(RSG_ENOMEM, "cannot allocate the %zu-byte intermediate of the two-pass images", mid_bytes);
     std::vector<PassParams> pps(2 * two.size());
-    using PassKey = std::tuple<int, int, int, int, int, int>;     // pass, dtype, C, npl, kt, stages
+    using PassKey = std::tuple<int, int, int, int, int, int, int>;   // pass, dtype, C, npl, kt, stages, rows
     std::map<PassKey, std::vector<int2>> pclasses;
     std::map<PassKey, uint32_t> plds;
     {
@@ -179,10 +179,11 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
             off += up(size_t(ip.H) * size_t(ip.W) * size_t(ip.C) * 4);
             for (int pass = 0; pass < 2; ++pass) {
                 pps[2 * j + pass] = pass_params(ip, pass, slice);
-                const PassKey key(pass, ip.dtype, pass == 0 ? ip.C : 1, ip.pnpl[pass], ip.kt, ip.pst[pass]);
+                const PassKey key(pass, ip.dtype, pass == 0 ? ip.C : 1, ip.pnpl[pass], ip.kt, ip.pst[pass],
+                                  ip.ptr[pass]);
                 const int rows = pps[2 * j + pass].rows;
                 auto& v = pclasses[key];
-                for (int blk = 0; blk < (rows + kPassRowsHost - 1) / kPassRowsHost; ++blk)
+                for (int blk = 0; blk < (rows + ip.ptr[pass] - 1) / ip.ptr[pass]; ++blk)
                     v.push_back(int2{int(2 * j + pass), blk});
                 plds[key] = std::max(plds[key], ip.plds[pass]);
             }
@@ -257,6 +258,7 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         b.npl = std::get<3>(kv.first);
         b.kt = std::get<4>(kv.first);
         b.stages = std::get<5>(kv.first);
+        b.tr = std::get<6>(kv.first);
         b.lds = plds[kv.first];
         b.d_pps = reinterpret_cast<const PassParams*>(ws + o_pp);
         b.d_tasks = reinterpret_cast<const int2*>(ws + o_task) + pos;

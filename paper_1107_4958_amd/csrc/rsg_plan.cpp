@@ -44,15 +44,20 @@ std::atomic<int> g_path_override{0};
 
 // Two-pass geometry: the smallest chunk (64 NPL samples) that holds the
 // window head (2R + 1) C and fits the LDS with one staging tile (0 if none
-// does), and two staging tiles when those fit too.
-int pass_npl_for(int C, int hw, int* stages)
+// does), and two staging tiles when those fit too; 16 rows per workgroup,
+// else 8 (multi-channel rows, C >= 2, whose windows are the widest).
+int pass_npl_for(int C, int hw, int* stages, int* tr)
 {
     const int n0 = (C == 3) ? 12 : 8;
-    for (int npl : {n0, 2 * n0})
-        if (hw <= kWave * npl && pass_lds_bytes(npl, hw, 1) <= kLdsLimit) {
-            *stages = pass_lds_bytes(npl, hw, 2) <= kLdsLimit ? 2 : 1;
-            return npl;
-        }
+    for (int rows : {kPassRowsHost, 8}) {
+        if (rows != kPassRowsHost && C < 2) break;
+        for (int npl : {n0, 2 * n0})
+            if (hw <= kWave * npl && pass_lds_bytes(npl, hw, 1, rows) <= kLdsLimit) {
+                *stages = pass_lds_bytes(npl, hw, 2, rows) <= kLdsLimit ? 2 : 1;
+                *tr = rows;
+                return npl;
+            }
+    }
     return 0;
 }
 
@@ -211,12 +216,12 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
 
     // ---- path: fused kernel, or two passes for wide boxes ----
     const int C = d.C;
-    p.pnpl[0] = pass_npl_for(C, (2 * R + 1) * C, &p.pst[0]);
-    p.pnpl[1] = pass_npl_for(1, 2 * R + 1, &p.pst[1]);
+    p.pnpl[0] = pass_npl_for(C, (2 * R + 1) * C, &p.pst[0], &p.ptr[0]);
+    p.pnpl[1] = pass_npl_for(1, 2 * R + 1, &p.pst[1], &p.ptr[1]);
     const bool two_ok = p.pnpl[0] > 0 && p.pnpl[1] > 0;
     if (two_ok) {
-        p.plds[0] = pass_lds_bytes(p.pnpl[0], (2 * R + 1) * C, p.pst[0]);
-        p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1, p.pst[1]);
+        p.plds[0] = pass_lds_bytes(p.pnpl[0], (2 * R + 1) * C, p.pst[0], p.ptr[0]);
+        p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1, p.pst[1], p.ptr[1]);
     }
     const int ov = g_path_override.load(std::memory_order_relaxed);
     int hs_t = 0;
@@ -256,7 +261,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         p.hs = d.H;
         p.nsegs = 1;
         p.step = step;
-        p.ntasks = (d.H + kPassRowsHost - 1) / kPassRowsHost + int((WoC + kPassRowsHost - 1) / kPassRowsHost);
+        p.ntasks = (d.H + p.ptr[0] - 1) / p.ptr[0] + int((WoC + p.ptr[1] - 1) / p.ptr[1]);
         p.lds_bytes = std::max(p.plds[0], p.plds[1]);
         *ip = p;
         return RSG_OK;

@@ -15,13 +15,14 @@
 // a window of (2R + 1) C running sums of the previous chunk, so every input
 // sample is loaded once per pass.
 //
-// Workgroup: kPassRows waves, one row each.  Chunk k of a row loads input
+// Workgroup: TR waves (16; 8 when a 16-row window would not fit the LDS),
+// one row each.  Chunk k of a row loads input
 // samples [k CW, (k + 1) CW) and emits outputs [k CW - R C, (k + 1) CW - R C)
 // (the window reaches R C samples beyond each output).  The window holds
 // running sums of positions [k CW - (2R + 1) C, (k + 1) CW); after the chunk
 // its last (2R + 1) C entries move to the front.  Outputs go to an LDS
-// staging tile [CW][kPassRows + 1], then the workgroup stores them
-// transposed: kPassRows consecutive elements per output row.  With two
+// staging tile [CW][TR + 1], then the workgroup stores them
+// transposed: TR consecutive elements per output row.  With two
 // staging tiles (ST = 2, when the LDS allows) chunk k + 1 fills the other
 // tile while chunk k's stores drain, and one barrier per chunk suffices.
 //
@@ -37,7 +38,7 @@
 namespace rsg {
 namespace dev {
 
-constexpr int kPassRows = 16;                  // waves (rows) per workgroup
+constexpr int kPassRows = 16;                  // waves (rows) per workgroup (8 for the widest windows)
 
 // What a pass writes.
 enum PassOut { kOutMidU32 = 0, kOutMidF32 = 1, kOutU8 = 2, kOutF32 = 3, kOutF16 = 4, kOutBF16 = 5 };
@@ -75,14 +76,13 @@ __device__ __forceinline__ int pass_clamp(int pos, int len, int boundary)
     return xe < 0 ? -1 : xe * C + c;
 }
 
-template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST, int TR>
 __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32_t* lds)
 {
     using Acc = typename TrIn::Acc;
     constexpr bool kInt = TrIn::kInt;
     constexpr int es = TrIn::kSize;
     constexpr int CW = kWave * NPL;
-    constexpr int TR = kPassRows;
     constexpr int SP = TR + 1;                     // staging pitch (words): conflict-free row writes
     static_assert(NPL % C == 0 && NPL % 4 == 0, "chunk must hold whole pixels and 16-byte groups");
     const int wave = threadIdx.x / kWave;
@@ -295,21 +295,21 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
     }
 }
 
-template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
-__global__ __launch_bounds__(kPassRows * kWave) void k_pass(PassParams p)
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST, int TR>
+__global__ __launch_bounds__(TR * kWave) void k_pass(PassParams p)
 {
     extern __shared__ uint32_t lds[];
-    pass_rows<TrIn, OUT, C, NPL, KT, ST>(p, blockIdx.x, lds);
+    pass_rows<TrIn, OUT, C, NPL, KT, ST, TR>(p, blockIdx.x, lds);
 }
 
 // The same pass over the row blocks of several images (one per workgroup).
-template <class TrIn, int OUT, int C, int NPL, int KT, int ST>
-__global__ __launch_bounds__(kPassRows * kWave) void k_pass_batch(const PassParams* __restrict__ pps,
-                                                                   const int2* __restrict__ tasks)
+template <class TrIn, int OUT, int C, int NPL, int KT, int ST, int TR>
+__global__ __launch_bounds__(TR * kWave) void k_pass_batch(const PassParams* __restrict__ pps,
+                                                           const int2* __restrict__ tasks)
 {
     extern __shared__ uint32_t lds[];
     const int2 t = tasks[blockIdx.x];
-    pass_rows<TrIn, OUT, C, NPL, KT, ST>(pps[t.x], t.y, lds);
+    pass_rows<TrIn, OUT, C, NPL, KT, ST, TR>(pps[t.x], t.y, lds);
 }
 
 }  // namespace dev

@@ -178,6 +178,8 @@ TWO_PASS_SHAPES = [
     # reflect: boxes many times wider than the axis, and every channel count
     (5, 3, 1, 8.0, 5, 2), (300, 1, 1, 3.0, 4, 2), (61, 211, 3, 6.0, 5, 2), (257, 259, 1, 32.0, 5, 2),
     (33, 2000, 4, 5.0, 3, 2), (97, 250, 2, 4.0, 4, 2),
+    # windows too wide for 16-row workgroups: pass A runs 8 rows per workgroup
+    (130, 300, 3, 64.0, 5, 0), (97, 520, 4, 40.0, 4, 2), (400, 90, 2, 64.0, 5, 1),
 ]
 
 
