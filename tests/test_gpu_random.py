@@ -1,0 +1,66 @@
+"""Seeded random cases through the C ABI against the oracle: shapes from 1
+to a few hundred per side, every dtype and channel count, K from 1 to 5,
+sigma log-uniform in [0.5, 40], all three boundaries, whichever path the
+planner picks (and the forced two-pass path for a third of the cases).
+uint8 bit-exact; FP32 within 1e-5 of max|input| (the scale of the summed
+values: the filter has unit DC gain, so max|ref| <= max|input|, and with zero
+extension and boxes wider than the image the output can be far smaller than
+the inputs whose running sums carry the rounding); FP16 / BF16 within one
+unit of the last place of the FP64 result."""
+import numpy as np
+import pytest
+
+import oracle
+import synthimg
+from gpu_util import decode, gpu_filter, half_ulp_diff
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+def _cases(n=48, seed=20261):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        H = int(np.exp(rng.uniform(0, np.log(400))))
+        W = int(np.exp(rng.uniform(0, np.log(400))))
+        C = int(rng.integers(1, 5))
+        dt = ["u8", "f32", "f16", "bf16"][int(rng.integers(0, 4))]
+        sigma = float(np.exp(rng.uniform(np.log(0.5), np.log(40.0))))
+        K = int(rng.integers(1, 6))
+        b = int(rng.integers(0, 3))
+        two = bool(i % 3 == 2)
+        out.append((i, H, W, C, dt, round(sigma, 3), K, b, two))
+    return out
+
+
+@pytest.mark.parametrize("i,H,W,C,dt,sigma,K,boundary,two", _cases())
+def test_random_case(i, H, W, C, dt, sigma, K, boundary, two):
+    import paper_1107_4958_amd as rsg
+    bx = oracle.boxes(sigma, K)
+    if dt == "u8" and bx["m"] is None:
+        pytest.skip("no integer weights at this sigma")
+    img = synthimg.image(H, W, C, dt, 900 + i)
+    if two:
+        try:
+            rsg.rsg_tune_path(rsg.RSG_PATH_TWO_PASS)
+            try:
+                out = gpu_filter(img, dt, sigma, K, boundary)
+            except rsg.RsgError as e:
+                assert e.code == rsg.RSG_EUNSUPPORTED          # window too wide for the two-pass path
+                pytest.skip("two-pass path infeasible: %s" % e)
+        finally:
+            rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+    else:
+        out = gpu_filter(img, dt, sigma, K, boundary)
+    if dt == "u8":
+        ref = oracle.box_filter_u8(img, bx["r"], bx["m"], bx["G"], boundary)
+        assert np.array_equal(out, ref)
+        return
+    ref = oracle.box_filter(decode(img, dt), bx["r"], bx["w32"].astype(np.float64), boundary)
+    if dt == "f32":
+        den = max(float(np.max(np.abs(decode(img, dt)))), 1e-30)
+        assert float(np.max(np.abs(out.astype(np.float64) - ref))) / den <= FP32_TOL
+    else:
+        assert half_ulp_diff(out, ref, dt) <= 1
