@@ -525,6 +525,8 @@ def main():
     ap.add_argument("--K", type=int, default=3)
     ap.add_argument("--dtype", default="f32", choices=["f32", "u8", "f16", "bf16"])
     ap.add_argument("--quick", action="store_true", help="headline and its uint8 form only")
+    ap.add_argument("--grid-only", action="store_true",
+                    help="only the sigma x K grid at 4096^2 (FP32 and uint8), for profiling its kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="first run 3 plain device copies of MIB MiB (a known-size reference for HBM counters)")
@@ -548,6 +550,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.grid_only:
+        imgs = {"f32": synthimg.image(4096, 4096, 1, "f32", 2), "u8": synthimg.image(4096, 4096, 1, "u8", 2)}
+        print(json.dumps({"sigma_K_grid_4096": sigma_k_grid(imgs, args.steps)}), flush=True)
+        return
 
     H = W = args.size
     img = synthimg.image(H, W, 1, args.dtype, 2)
