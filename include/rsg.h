@@ -14,7 +14,11 @@
  *   - box half-widths and weights come from an exhaustive fit at
  *     sigma0 = 100/pi under the quadratic-form error of Section 4.1
  *     (Eq. mahal, autocorrelation of a 1/f spectrum), rescaled to the
- *     requested sigma by Eq. scale1 / scale2 (Section 4.2).
+ *     requested sigma by Eq. scale1 / scale2 (Section 4.2); other fit methods
+ *     (l2 error, a direct fit at sigma) and caller-supplied boxes are offered
+ *     too;
+ *   - beyond 2D images: strided (downsampling) output and FP32 volumes (one
+ *     more 1D pass along z).
  *
  * Conventions for every entry point:
  *   - functions never throw; they return RSG_OK (0) or a negative rsg_status;

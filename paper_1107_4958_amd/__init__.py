@@ -6,11 +6,14 @@ PyTorch tensors are used only as device memory and their streams.  If the
 library has not been built this module raises ImportError: there is no
 fallback path.
 
-Entry points carry the C names (``rsg_fit_boxes``, ``rsg_gauss_filter``,
-``rsg_filter_batch_workspace``, ``rsg_filter_batch``, ``rsg_server_create``,
-``rsg_submit``, ``rsg_poll``, ``rsg_server_destroy``, ``rsg_plan_shape``,
-``rsg_tune_override``, ``rsg_tune_path``, ``rsg_last_error``); ``filter_tensor`` and
-``filter_batch_tensors`` wrap them for torch tensors.
+Entry points carry the C names (``rsg_fit_boxes``, ``rsg_fit_boxes_ex``,
+``rsg_gauss_filter``, ``rsg_box_filter``, ``rsg_gauss_filter_strided``,
+``rsg_gauss_filter_3d``, ``rsg_filter_batch_workspace``, ``rsg_filter_batch``,
+``rsg_server_create``, ``rsg_submit``, ``rsg_poll``, ``rsg_server_destroy``,
+``rsg_plan_shape``, ``rsg_tune_override``, ``rsg_tune_path``,
+``rsg_last_error``); ``filter_tensor``, ``filter_strided_tensor``,
+``filter_volume_tensor`` and ``filter_batch_tensors`` wrap them for torch
+tensors.
 
 Unless ``RSG_TUNE_TABLE`` is already set, the library reads the segment
 heights measured by ``autotune.py`` from ``tune_gfx950.txt`` beside it.

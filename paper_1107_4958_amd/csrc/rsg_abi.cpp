@@ -1,5 +1,7 @@
 // C ABI entry points (include/rsg.h).  Marshalling and validation only; the
-// filtering itself runs in rsg_kernels.hip, the fit in rsg_fit.cpp.
+// filtering runs in the kernels of rsg_device.h, rsg_twopass.h and
+// rsg_zpass.h (instantiated in rsg_k_*.hip), the fit in rsg_fit.cpp, volumes
+// in rsg_volume.cpp and serving in rsg_server.cpp.
 #include "rsg_internal.h"
 
 #include <cstdarg>

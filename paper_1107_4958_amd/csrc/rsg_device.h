@@ -1,10 +1,13 @@
 // Device code of the fused running-sum Gaussian filter for gfx950 (MI355X).
 //
-// One 64-lane wave owns one task: a strip of 64 consecutive sample-columns
-// (lane c owns column s0 + c in the column pass) and a segment of hs output
-// rows of one image.  It streams down the image in groups of G input rows:
+// A task is a strip of 64 consecutive sample-columns (lane c owns column
+// s0 + c in the column pass) and a segment of hs output rows of one image.
+// It streams down the image in groups of G input rows, either on one wave
+// (both passes, software-pipelined: stream_task) or on a workgroup whose
+// row-pass and column-pass waves hand each group over through LDS
+// (stream_task_pc, the default):
 //
-//   row pass (Section 3.3, Eq. alg1 / indep, along x): the wave splits into
+//   row pass (Section 3.3, Eq. alg1 / indep, along x): the row-pass wave splits into
 //     G = 64 / SEG segments of SEG lanes; segment j takes input row
 //     (group start + j), lane q of the segment holds NPL consecutive samples
 //     of the row span [s0 - (R+1)C, s0 + 64 + RC) (border samples replicated,
@@ -24,9 +27,10 @@
 // loads stay in flight while the current one is processed.
 //
 // FP32 / FP16 / BF16 accumulate in FP32.  Running sums are tile-local and
-// offset: each row subtracts its first span sample (added back through the
-// DC gain of the boxes) and each column its first T value, which keeps the
-// summed magnitudes, and hence the rounding of the differences, small.
+// offset: each group of rows subtracts one of its samples (added back
+// through the DC gain of the boxes) and each column its first T value, which
+// keeps the summed magnitudes, and hence the rounding of the differences,
+// small.  Both forms perform the same FP32 operations in the same order.
 // uint8 uses exact uint32 arithmetic (differences are exact modulo 2^32 and
 // every box sum is < 2^32), integer weights m_k and one exact rounding of
 // U / G^2.

@@ -1,7 +1,8 @@
 // Host-side dispatch from a planned image (or batch class) to the kernel
 // instantiation for its element type, channel count, scan chunk and tap
-// count.  Included once per element type so the instantiations compile in
-// parallel translation units.
+// count (fused kernel), or pass, chunk, staging and rows per workgroup
+// (two-pass kernel).  Included once per element type so the instantiations
+// compile in parallel translation units.
 #pragma once
 
 #include "rsg_device.h"

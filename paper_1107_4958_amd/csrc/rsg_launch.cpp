@@ -1,6 +1,8 @@
-// Launch paths: one image (one fused kernel launch) and batches (one
-// persistent launch per (element type, channel count, tap count) class,
-// all on the caller's stream).
+// Launch paths, all on the caller's stream: one image (one fused kernel
+// launch, or the two launches of the two-pass path around a stream-ordered
+// intermediate) and batches (one persistent launch per fused class of
+// element type, channel count, tap count and form, then the two-pass images'
+// row blocks grouped per pass instantiation).
 #include "rsg_internal.h"
 
 #include <algorithm>

@@ -1,13 +1,16 @@
-// Tile planning: validates one image descriptor, fits its boxes (cached) and
-// chooses the scan chunk and segment height of its tasks (strips are 64
-// sample-columns wide: one column per lane).
+// Tile planning: validates one image descriptor, fits its boxes (cached, or
+// checks the caller's), chooses the path (fused kernel, or two passes for
+// wide boxes and strided output) and, for the fused path, the scan chunk and
+// segment height of its tasks (strips are 64 sample-columns wide: one column
+// per lane); for the two-pass path, the chunk, staging and rows per
+// workgroup of each pass.
 //
 // The choice is a pure function of the image's own parameters (dtype, C, H,
 // W, the box half-widths, boundary, pointer alignment), never of the batch it
 // arrives in, so an image filters to the same bits alone or in a mix.  Shapes
-// come from a tuning table (segment heights measured on the device by the
-// package's autotune.py) when one is loaded, otherwise from the built-in rule
-// below.
+// come from a tuning table (segment heights and the path, measured on the
+// device by the package's autotune.py) when one is loaded, otherwise from
+// the built-in rule below.
 #include "rsg_internal.h"
 
 #include <algorithm>
