@@ -147,10 +147,12 @@ int rsg_box_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtyp
  * contiguous ceil(H/step) x ceil(W/step) x C image to d_dst (Eq. indep
  * evaluated on a sparser output grid, Section 3.3; the running sums still
  * cover every input sample).  Boxes: `boxes` if not NULL (as
- * rsg_box_filter), else rsg_fit_boxes(sigma, K).  For step > 1 it runs on
- * the two-pass path (row filter keeping every step-th pixel into an
- * intermediate of ceil(W/step) C x H four-byte words, then the column filter
- * keeping every step-th row); step = 1 is rsg_gauss_filter / rsg_box_filter.
+ * rsg_box_filter), else rsg_fit_boxes(sigma, K).  The path is the one
+ * rsg_gauss_filter would take: the fused kernel (its column pass stores
+ * every step-th row and pixel only), or for wide boxes the two-pass path
+ * (row filter keeping every step-th pixel into an intermediate of
+ * ceil(W/step) C x H four-byte words, then the column filter keeping every
+ * step-th row); step = 1 is rsg_gauss_filter / rsg_box_filter.
  * Errors: as rsg_gauss_filter / rsg_box_filter; RSG_EINVAL (step < 1);
  * RSG_EUNSUPPORTED (boxes too wide for the two-pass path: C = 3 beyond
  * r_max ~ 127, C = 4 beyond ~ 95). */

@@ -780,10 +780,24 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
         }
     } else {
         // ---------------- column pass ----------------
-        const char* dbase = reinterpret_cast<char*>(ip.dst) + tg.slice_off + int64_t(tg.y0) * dstride;
-        const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(dbase, int64_t(tg.hs - 1) * dstride + int64_t(WC) * es);
+        // Output rows of this task: y0 .. y0 + hs - 1, or with a strided
+        // output (every ostep-th row and pixel, compacted) the kept rows
+        // oq0 .. oq1 - 1 of the output image; rows outside the descriptor
+        // and dropped columns are stored to out-of-range offsets.
+        const int ostep = ip.step > 1 ? ip.step : 1;
         const int s = tg.s0 + lane;
-        const uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
+        int oq0 = tg.y0, nrows = tg.hs, orow_len = WC;
+        uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
+        if (ostep > 1) {
+            oq0 = (tg.y0 + ostep - 1) / ostep;
+            nrows = (tg.y0 + tg.hs - 1) / ostep - oq0 + 1;
+            orow_len = (W + ostep - 1) / ostep * C;
+            const int x = s / C;
+            ocol = (s < WC && x % ostep == 0) ? uint32_t(((x / ostep) * C + (s - x * C)) * es) : kDropColumn;
+        }
+        const char* dbase = reinterpret_cast<char*>(ip.dst) + tg.slice_off + int64_t(oq0) * dstride;
+        const __amdgpu_buffer_rsrc_t rs_dst =
+            make_rsrc(dbase, nrows > 0 ? int64_t(nrows - 1) * dstride + int64_t(orow_len) * es : 0);
         const uint32_t dstr = uint32_t(dstride);
         Acc colacc = Acc(0);
         float c2 = 0.0f;
@@ -825,10 +839,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
                 }
             }
             const int it0 = g * G;
-            const uint32_t og = (it0 >= tg.emit0) ? ocol + uint32_t(it0 - tg.emit0) * dstr : uint32_t(kDropOffset);
-#pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int voff = int(og + uint32_t(j) * dstr);
+            auto emit = [&](int j, int voff) {
                 if constexpr (kInt) {
                     double U = 0.0;
 #pragma unroll
@@ -841,6 +852,23 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
 #pragma unroll
                     for (int k = 0; k < KT; ++k) o = fmaf(wf[k], rv[j][2 * k] - rv[j][2 * k + 1], o);
                     store_out<Tr>(rs_dst, voff, 0, o);
+                }
+            };
+            if (ostep == 1) {
+                const uint32_t og = (it0 >= tg.emit0) ? ocol + uint32_t(it0 - tg.emit0) * dstr : uint32_t(kDropOffset);
+#pragma unroll
+                for (int j = 0; j < G; ++j) emit(j, int(og + uint32_t(j) * dstr));
+            } else {
+                // strided output: rows y = 0, ostep, 2 ostep, ... only (a
+                // uniform test per row), stored at output row y / ostep
+                const int yb = tg.y0 + it0 - tg.emit0;      // image row of this group's first output
+                int q = floor_div(yb, ostep);
+                int rr = yb - q * ostep;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    if (rr == 0 && it0 + j >= tg.emit0)
+                        emit(j, int(ocol + uint32_t(q - oq0) * dstr));
+                    if (++rr == ostep) { rr = 0; ++q; }
                 }
             }
             slot0 += G;

@@ -231,7 +231,9 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t);
     bool two = two_ok && (tabled ? hs_t < 0 : R * C >= kTwoPassMinRC);
     if (ov == 1 || ov == 3) two = false;
-    if (ov == 2 || step > 1) {      // strided output exists on the two-pass path only
+    // strided output: the fused two-wave form (which stores every step-th row
+    // and pixel) when the fused path is chosen, else the two-pass path
+    if (ov == 2 || (step > 1 && ov == 3)) {
         if (!two_ok) return set_error(RSG_EUNSUPPORTED, "two-pass path: box half-width %d too wide for C=%d", R, C);
         two = true;
     }
@@ -313,6 +315,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
                              (long long)stride_b, R);
         }
     }
+    p.step = step;
     p.hs = hs;
     p.nsegs = (d.H + hs - 1) / hs;
     const int64_t nt = int64_t(p.nstrips) * p.nsegs;
