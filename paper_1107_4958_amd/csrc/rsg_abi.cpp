@@ -4,6 +4,7 @@
 // in rsg_volume.cpp and serving in rsg_server.cpp.
 #include "rsg_internal.h"
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -41,6 +42,33 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
             return set_error(rc, "image %d: %s", i, msg.c_str());
         }
         total += imgs[i].ntasks;                  // fused tasks or two-pass row blocks
+    }
+    // uint8 results are exact integers whatever the segment height, so a batch
+    // may give its fused uint8 images longer segments (fewer halo rows) as
+    // long as the batch keeps enough tasks to fill the device; float images
+    // keep their own plan (their rounding follows the segment boundaries)
+    if (hs_pref <= 0) {
+        constexpr int64_t kTarget = 4096;
+        int64_t fixed = 0, strips = 0;
+        for (int i = 0; i < n; ++i) {
+            if (imgs[i].path != kPathFused) continue;
+            if (imgs[i].dtype == RSG_U8) strips += imgs[i].nstrips;
+            else fixed += imgs[i].ntasks;
+        }
+        if (strips > 0) {
+            const int64_t segs = std::max<int64_t>(1, (kTarget - fixed + strips - 1) / strips);
+            for (int i = 0; i < n; ++i) {
+                ImgParams& ip = imgs[i];
+                if (ip.path != kPathFused || ip.dtype != RSG_U8) continue;
+                const int hs = int(std::max<int64_t>(ip.hs, (ip.H + segs - 1) / segs));
+                if (hs == ip.hs) continue;
+                ImgParams longer;
+                if (plan_image(d[i], &longer, 1, hs) == RSG_OK && longer.path == kPathFused) {
+                    total += int64_t(longer.ntasks) - ip.ntasks;
+                    ip = longer;
+                }
+            }
+        }
     }
     if (total > (int64_t(1) << 30)) return set_error(RSG_EUNSUPPORTED, "batch too large");
     tasks.reserve(size_t(total));
