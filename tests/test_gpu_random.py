@@ -64,3 +64,37 @@ def test_random_case(i, H, W, C, dt, sigma, K, boundary, two):
         assert float(np.max(np.abs(out.astype(np.float64) - ref))) / den <= FP32_TOL
     else:
         assert half_ulp_diff(out, ref, dt) <= 1
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_random_batch_identical_to_alone(seed):
+    """24 random images (every dtype, C, K, boundary; sides up to 700) in one
+    batched launch: each bit-identical to its single-image result (uint8
+    images take longer segments in a batch: exact arithmetic keeps the bits),
+    and uint8 equal to the oracle."""
+    import torch
+    import paper_1107_4958_amd as rsg
+    from gpu_util import from_device, to_device
+    rng = np.random.default_rng(seed)
+    boundary = int(rng.integers(0, 3))
+    items = []
+    for i in range(24):
+        H, W = int(rng.integers(1, 700)), int(rng.integers(1, 700))
+        C = int(rng.integers(1, 5))
+        dt = ["u8", "f32", "f16", "bf16"][int(rng.integers(0, 4))]
+        sigma = float(np.exp(rng.uniform(np.log(0.7), np.log(30.0))))
+        K = int(rng.integers(1, 6))
+        if dt == "u8" and oracle.boxes(sigma, K)["m"] is None:
+            dt = "f32"
+        items.append((synthimg.image(H, W, C, dt, 1000 * seed + i), dt, sigma, K))
+    srcs = [to_device(img, dt) for img, dt, _, _ in items]
+    dsts = [torch.full_like(s, 0) for s in srcs]
+    rsg.filter_batch_tensors(srcs, dsts, [it[2] for it in items], [it[3] for it in items], boundary=boundary)
+    torch.cuda.synchronize()
+    for (img, dt, sigma, K), s, d in zip(items, srcs, dsts):
+        got = from_device(d, dt)
+        alone = gpu_filter(img, dt, sigma, K, boundary)
+        assert np.array_equal(got.view(np.uint8), alone.view(np.uint8)), (img.shape, dt, sigma, K)
+        if dt == "u8":
+            b = oracle.boxes(sigma, K)
+            assert np.array_equal(got, oracle.box_filter_u8(img, b["r"], b["m"], b["G"], boundary))
