@@ -196,7 +196,9 @@ int rsg_filter_batch_workspace(const rsg_image_desc* d, int n, size_t* bytes);
  * the work list are copied into it asynchronously on `stream`, so the
  * workspace must not be reused until the stream has passed this call).
  * Each image's result is bit-identical to rsg_gauss_filter on that image
- * alone (tile shapes are a function of the image only).
+ * alone: float images keep their single-image tile plan; uint8 images may
+ * get longer segments in a batch (fewer halo rows), which cannot change
+ * their exact integer results.
  * Errors: as rsg_gauss_filter, RSG_ENOMEM (ws_bytes too small). */
 int rsg_filter_batch(const rsg_image_desc* d, int n, void* d_workspace, size_t ws_bytes,
                      void* stream);
@@ -261,8 +263,9 @@ int rsg_server_destroy(rsg_server* s);
  * are compared but never dereferenced.  Segment heights come from the tuning
  * table named by the environment variable RSG_TUNE_TABLE (read once, lines
  * "dtype C rlo rhi nlo nhi hs", with R the largest box half-width and n the
- * number of 64-sample strips times H), else from a built-in rule; the plan
- * never depends on other images of a batch.  Any output pointer may be NULL.
+ * number of 64-sample strips times H), else from a built-in rule.  This is
+ * the image's own plan; in a batch, uint8 images may get longer segments
+ * (same results).  Any output pointer may be NULL.
  * Errors: as rsg_gauss_filter. */
 int rsg_plan_shape(const rsg_image_desc* d, int32_t* seg_height, int32_t* tasks, uint32_t* lds_bytes);
 

@@ -7,8 +7,9 @@
 // launch on the slot's stream.  Launches on different streams overlap on the
 // device, so requests that arrive while earlier ones run start as soon as a
 // slot frees instead of waiting for the whole device to drain.  Completion is
-// detected with one event per launch.  Tile shapes depend on each image
-// alone, so a request filters to the same bits whatever it is batched with.
+// detected with one event per launch.  A request filters to the same bits
+// whatever it is batched with (float tile shapes depend on each image alone;
+// uint8 results are exact whatever the segment height).
 #include "rsg_internal.h"
 
 #include <algorithm>
