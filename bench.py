@@ -579,6 +579,12 @@ def main():
                    "H": H, "W": W, "C": 1, "sigma": args.sigma, "K": args.K},
         "roofline": roofline(args.dtype, H, W, 1, ms, traffic_record(key)),
         "parity_spot_check": sampled_parity(img, out, args.dtype, args.sigma, args.K),
+        # the paper states no run times, throughputs or hardware: only the
+        # per-pixel operation count (Table 1) and a speed ranking whose figure
+        # carries no data in its source
+        "paper_context": {"published_timings": None,
+                          "ops_per_pixel": 6 * args.K, "ops_note": "4K additions + 2K multiplications per pixel (Table 1)",
+                          "achieved_gops": round(6 * args.K * gpx, 1)},
     }
     imgs = {args.dtype: img}
     if args.dtype != "u8":          # the uint8 form of the same configuration (exact integer path)
