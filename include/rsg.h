@@ -210,7 +210,8 @@ typedef struct rsg_server rsg_server;
 
 /* d_arena / arena_bytes: caller-owned device memory the server carves its
  * per-launch workspaces from.  hbm_budget: admission limit on the sum of the
- * in-flight requests' image bytes (src + dst); 0 means unlimited.
+ * in-flight requests' device bytes (src + dst, plus the intermediate of
+ * requests planned on the two-pass path); 0 means unlimited.
  * max_inflight: launches outstanding at once (1..64); n_streams: HIP streams
  * the server creates (1..8); queue_depth: requests waiting for admission
  * (>= 1); max_batch: requests per launch (>= 1). */
@@ -259,7 +260,8 @@ int rsg_server_destroy(rsg_server* s);
  * samples of a row and streams 2R + 1 extra rows above its segment), the
  * number of tasks and the LDS bytes per task.  For an image planned on the
  * two-pass path the segment height is H, the tasks are the workgroups of
- * both passes (16 rows each) and the LDS is the larger pass's.  Host-only: d->src and d->dst
+ * both passes (16 rows each; 8 in pass A for the widest multi-channel
+ * windows) and the LDS is the larger pass's.  Host-only: d->src and d->dst
  * are compared but never dereferenced.  Segment heights come from the tuning
  * table named by the environment variable RSG_TUNE_TABLE (read once, lines
  * "dtype C rlo rhi nlo nhi hs", with R the largest box half-width and n the
@@ -283,8 +285,9 @@ int rsg_tune_override(int32_t seg_height);
  * filter into an FP32 / uint32 intermediate stored transposed, then the same
  * on the intermediate; the intermediate, 4 H W C bytes, is allocated and
  * released in stream order), 3 forces the fused kernel with one wave per
- * task (the form batched launches use).  Results agree to FP32 rounding and
- * are bit-identical for uint8.  For the autotuner and tests.
+ * task (software-pipelined; batches planned under it use the one-wave batch
+ * kernel too).  The fused forms give identical bits; results of the fused
+ * and two-pass paths agree to FP32 rounding and are bit-identical for uint8.  For the autotuner and tests.
  * Errors: RSG_EINVAL (path not in 0..3); later plans return
  * RSG_EUNSUPPORTED when the forced path cannot hold the boxes. */
 int rsg_tune_path(int32_t path);
