@@ -239,3 +239,39 @@ def test_volume_validation():
     assert lib.rsg_gauss_filter_3d(A, B, 4, 8, 8, 5, rsg.RSG_F32, 2.0, 3, None, 0, None) == rsg.RSG_EINVAL
     assert lib.rsg_gauss_filter_3d(A, ctypes.c_void_p(0x100000 + 64), 4, 8, 8, 1, rsg.RSG_F32, 2.0, 3, None, 0,
                                    None) == rsg.RSG_EINVAL
+
+
+def test_fits_and_plans_from_many_threads():
+    """Host entry points called from 8 threads at once (ctypes releases the
+    GIL): the fit caches and the tuning-table load give every thread the
+    sequential results."""
+    import threading
+    rsg = _rsg()
+    jobs = [(s, K, m) for s in (0.6, 1.3, 2.7, 5.5, 9.0) for K in (3, 4, 5) for m in (0, 1, 2)]
+
+    def key(b):
+        return (b.K, tuple(b.r[:b.K]), tuple(b.w[:b.K]), tuple(b.m[:b.K]), b.G)
+
+    seq = {j: key(rsg.rsg_fit_boxes_ex(*j)) for j in jobs}
+    out, errors = {}, []
+
+    def worker(t):
+        try:
+            for j in jobs[t::8] + jobs[::-1][t::8]:
+                got = key(rsg.rsg_fit_boxes_ex(*j))
+                out.setdefault(j, set()).add(got)
+                d = rsg.rsg_image_desc()
+                d.src, d.dst = 0x10000, 0x100000000000
+                d.H, d.W, d.C, d.dt, d.sigma, d.K, d.b = 300 + t, 200, 1 + t % 4, t % 4, j[0], j[1], t % 3
+                rsg.rsg_plan_shape(d)
+        except Exception as e:          # noqa: BLE001  (reported below)
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(8)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for j, got in out.items():
+        assert got == {seq[j]}, j
