@@ -98,3 +98,58 @@ def test_random_batch_identical_to_alone(seed):
         if dt == "u8":
             b = oracle.boxes(sigma, K)
             assert np.array_equal(got, oracle.box_filter_u8(img, b["r"], b["m"], b["G"], boundary))
+
+
+def _strided_cases(n=16, seed=555):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        H, W = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        C = int(rng.integers(1, 5))
+        dt = ["u8", "f32"][int(rng.integers(0, 2))]
+        sigma = round(float(np.exp(rng.uniform(np.log(0.6), np.log(40.0)))), 3)
+        K = int(rng.integers(1, 6))
+        out.append((i, H, W, C, dt, sigma, K, int(rng.integers(0, 3)), int(rng.integers(1, 9))))
+    return out
+
+
+@pytest.mark.parametrize("i,H,W,C,dt,sigma,K,boundary,step", _strided_cases())
+def test_random_strided(i, H, W, C, dt, sigma, K, boundary, step):
+    """Strided output on whichever path the planner picks: every step-th row
+    and pixel of the oracle's full result."""
+    import torch
+    import paper_1107_4958_amd as rsg
+    from gpu_util import from_device, to_device
+    bx = oracle.boxes(sigma, K)
+    if dt == "u8" and bx["m"] is None:
+        pytest.skip("no integer weights at this sigma")
+    img = synthimg.image(H, W, C, dt, 2000 + i)
+    try:
+        out = from_device(rsg.filter_strided_tensor(to_device(img, dt), sigma, K, step, boundary), dt)
+    except rsg.RsgError as e:
+        assert e.code == rsg.RSG_EUNSUPPORTED
+        pytest.skip("boxes too wide for the strided paths: %s" % e)
+    torch.cuda.synchronize()
+    if dt == "u8":
+        ref = oracle.box_filter_u8(img, bx["r"], bx["m"], bx["G"], boundary)[::step, ::step]
+        assert out.shape == ref.shape and np.array_equal(out, ref)
+    else:
+        ref = oracle.box_filter(img.astype(np.float64), bx["r"], bx["w32"].astype(np.float64), boundary)[::step, ::step]
+        assert out.shape == ref.shape
+        assert float(np.max(np.abs(out - ref))) / max(float(np.max(np.abs(img))), 1e-30) <= FP32_TOL
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33, 34, 35, 36])
+def test_random_volume(seed):
+    import torch
+    import paper_1107_4958_amd as rsg
+    rng = np.random.default_rng(seed)
+    D, H, W, C = int(rng.integers(1, 40)), int(rng.integers(1, 90)), int(rng.integers(1, 90)), int(rng.integers(1, 5))
+    sigma = round(float(np.exp(rng.uniform(np.log(0.6), np.log(12.0)))), 3)
+    K, boundary = int(rng.integers(1, 6)), int(rng.integers(0, 3))
+    vol = rng.uniform(0, 255, size=(D, H, W, C) if C > 1 else (D, H, W)).astype(np.float32)
+    src = torch.from_numpy(vol).cuda()
+    out = rsg.filter_volume_tensor(src, sigma, K, boundary).cpu().numpy()
+    bx = oracle.boxes(sigma, K)
+    ref = oracle.box_filter_3d(vol.astype(np.float64), bx["r"], bx["w32"].astype(np.float64), boundary)
+    assert float(np.max(np.abs(out - ref))) / 255.0 <= FP32_TOL, (D, H, W, C, sigma, K, boundary)
