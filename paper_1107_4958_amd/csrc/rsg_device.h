@@ -491,13 +491,17 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     // exactly the same values, so every form agrees bit for bit.)
     auto col_push = [&]() {
         const int wbase = slot0 * RP + lane;
-        const int mbase = (slot0 == 0 ? L : slot0) * RP + lane;
+        Acc cj[G];
 #pragma unroll
         for (int j = 0; j < G; ++j) {
             if constexpr (kInt) colacc += Tq[j];
             else colacc += Tq[j] - c2;
+            cj[j] = colacc;
             ring[wbase + j * RP] = colacc;
-            ring[mbase + j * RP] = colacc;          // mirror copy (same slot unless slot0 == 0)
+        }
+        if (slot0 == 0) {                           // slots 0 .. G-1 also live at L .. L+G-1
+#pragma unroll
+            for (int j = 0; j < G; ++j) ring[(L + j) * RP + lane] = cj[j];
         }
     };
 
@@ -816,13 +820,17 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
                 }
             }
             const int wbase = slot0 * RP + lane;
-            const int mbase = (slot0 == 0 ? L : slot0) * RP + lane;
+            Acc cj[G];
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 if constexpr (kInt) colacc += Qs[j * kWave + lane];
                 else colacc += Qs[j * kWave + lane] - c2;
+                cj[j] = colacc;
                 ring[wbase + j * RP] = colacc;
-                ring[mbase + j * RP] = colacc;
+            }
+            if (slot0 == 0) {                       // slots 0 .. G-1 also live at L .. L+G-1
+#pragma unroll
+                for (int j = 0; j < G; ++j) ring[(L + j) * RP + lane] = cj[j];
             }
             wave_lds_fence();
             Acc rv[G][2 * KT];
