@@ -692,12 +692,25 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
             }
         }
         const int sstride32 = int(sstride);
-        auto load = [&](Chunk<Tr, NPL>& ch, int st) {    // the group of step st
+        // 4-byte samples on a border task: a lane whose chunk lies inside the
+        // row loads it as vectors, the others per element; each lane's other
+        // load reads out of range (zeros), and the two are ORed when the group
+        // is used, so no branch diverges and every wait stays exact
+        constexpr bool kSplit = EDGE && Tr::kSize == 4;
+        const bool lane_vec = ip.vec && cs >= 0 && cs + NPL <= WC;
+        auto load = [&](Chunk<Tr, NPL>& ch, Chunk<Tr, NPL>& ech, int st) {    // the group of step st
             const int y = tg.ybase + (st * NPR + wave) * G + jrow;
             const int ye = ext_index(y, H, boundary);
             const bool zero_row = ye < 0;
             const int rowoff = (zero_row ? 0 : ye - y_lo) * sstride32;
-            if constexpr (EDGE) {
+            if constexpr (kSplit) {
+                load_chunk_vec<Tr, NPL>(ch, rs_src, (lane_vec && !zero_row) ? vec_voff + rowoff : kDropOffset, 0);
+                int vo[NPL];
+#pragma unroll
+                for (int i = 0; i < NPL; ++i)
+                    vo[i] = (lane_vec || eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
+                load_chunk_elem<Tr, NPL>(ech, rs_src, vo, 0);
+            } else if constexpr (EDGE) {
                 int vo[NPL];
 #pragma unroll
                 for (int i = 0; i < NPL; ++i) vo[i] = (eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
@@ -713,10 +726,11 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
             tm[k] = tg.off + lane - (ip.r[k] + 1) * C;
         }
         Chunk<Tr, NPL> buf[PF];
+        Chunk<Tr, NPL> ebuf[kSplit ? PF : 1];
 #pragma unroll
         for (int b = 0; b < PF; ++b) {          // this wave issues loads only: every wait is exact
             __builtin_amdgcn_sched_barrier(0);
-            load(buf[b], b);
+            load(buf[b], ebuf[kSplit ? b : 0], b);
         }
         __builtin_amdgcn_sched_barrier(0);
         for (int g = 0; g < nsteps; g += PF) {
@@ -724,6 +738,10 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
             for (int b = 0; b < PF; ++b) {
                 const int gg = g + b;
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (kSplit) {
+#pragma unroll
+                    for (int k = 0; k < Chunk<Tr, NPL>::kWords; ++k) buf[b].w[k] |= ebuf[b].w[k];
+                }
                 Acc v[NPL];
                 float off = 0.0f;
                 if constexpr (!kInt) {
@@ -735,7 +753,7 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
                     for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i);
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                load(buf[b], gg + PF);
+                load(buf[b], ebuf[kSplit ? b : 0], gg + PF);
                 __builtin_amdgcn_sched_barrier(0);
                 // running sums along the row (Eq. alg1)
 #pragma unroll
