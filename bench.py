@@ -527,6 +527,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline and its uint8 form only")
     ap.add_argument("--grid-only", action="store_true",
                     help="only the sigma x K grid at 4096^2 (FP32 and uint8), for profiling its kernels")
+    ap.add_argument("--only", choices=["strided", "volume", "batch", "precision"],
+                    help="only one of the other workloads (--steps timed repetitions), for profiling its kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="first run 3 plain device copies of MIB MiB (a known-size reference for HBM counters)")
@@ -554,6 +556,13 @@ def main():
     if args.grid_only:
         imgs = {"f32": synthimg.image(4096, 4096, 1, "f32", 2), "u8": synthimg.image(4096, 4096, 1, "u8", 2)}
         print(json.dumps({"sigma_K_grid_4096": sigma_k_grid(imgs, args.steps)}), flush=True)
+        return
+
+    if args.only:
+        run = {"strided": ("strided_8192", strided_workload), "volume": ("volume_256", volume_workload),
+               "batch": ("batch", batch_workload), "precision": ("precision_8192", precision_workload)}
+        name, fn = run[args.only]
+        print(json.dumps({name: fn(args.steps)}), flush=True)
         return
 
     H = W = args.size
