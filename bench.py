@@ -227,7 +227,7 @@ def fit_study():
 def strided_workload(steps):
     """Strided (downsampling) evaluation at 8192 x 8192 FP32, sigma = 8,
     K = 3: every step-th row and pixel for step in {1, 2, 4} (step 1 through
-    the same two-pass path), against the full single-image filter.
+    the strided entry point too), against the full single-image filter.
     Algorithmic bytes: the input read once plus the strided output written
     once; sampled parity against the oracle."""
     import torch
