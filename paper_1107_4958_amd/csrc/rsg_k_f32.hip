@@ -27,7 +27,7 @@ int launch_pass_batch_f32(const PassBatchLaunch& b, hipStream_t stream)
 
 int launch_zpass_f32(const ZParams& zp, int kt, int wpb, hipStream_t stream)
 {
-    constexpr int PFZ = 8;
+    constexpr int PFZ = 4;                  // slices prefetched ahead (4 measured 0-5 % faster than 8 and 16)
     const void* fn = nullptr;
     switch (kt) {
     case 3: fn = reinterpret_cast<const void*>(dev::k_zpass<3, PFZ>); break;
