@@ -292,3 +292,62 @@ def test_direct_fit_removes_the_small_sigma_degeneracy(sigma, k):
     assert len(set(d["r"].tolist())) == k
     assert abs(float(np.sum(d["w"] * (2 * d["r"] + 1))) - 1.0) < 1e-14
     assert l2(d) < l2(s)
+
+
+# --------------------------------------------------------------------------
+# Eq. scale2 away from sigma0, pinned to Table 2's printed constants
+# --------------------------------------------------------------------------
+def _printed_slices(k):
+    """Slice weights c_i - c_{i+1} of Table 2's printed constants (Section 3.2
+    reading: c_{k+1} = 0), normalised to sum 1."""
+    c = np.append(np.array(GOLD["table2"][str(k)]["c"], dtype=np.float64), 0.0)
+    d = c[:-1] - c[1:]
+    return d / d.sum()
+
+
+@pytest.mark.parametrize("sigma", [2.0, 8.0, 13.7, 64.0])
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_scale2_area_factor_on_printed_table(sigma, k):
+    """Section 4.2, Eq. scale2: a slice of half-width p_i at sigma0 becomes a
+    box of 2 r_i + 1 samples whose weight carries the area factor
+    p_i / (2 r_i + 1), up to one global factor.  Fed Table 2's printed
+    partition and constants, the scaled weights with that factor undone,
+    w_i (2 r_i + 1) / p_i, are proportional to the printed slice weights
+    c_i - c_{i+1} at every sigma, and the kernel has unit DC gain."""
+    row = GOLD["table2"][str(k)]
+    p = np.array(row["p"], dtype=np.int64)
+    r, w, _ = oracle.scale(sigma, row["p"], row["c"])
+    assert list(r) == [math.floor(sigma * math.pi * pi / 100.0 + 1e-9) for pi in row["p"]]
+    v = w * (2 * r.astype(np.float64) + 1) / p
+    assert np.max(np.abs(v / v.sum() - _printed_slices(k))) <= 1e-12
+    assert abs(float(np.sum(w * (2 * r.astype(np.float64) + 1))) - 1.0) <= 1e-14
+
+
+@pytest.mark.parametrize("sigma", [2.0, 8.0, 13.7, 64.0])
+@pytest.mark.parametrize("k", [3, 5])
+def test_scale2_on_the_oracle_fit_matches_printed_slices(sigma, k):
+    """The same through the oracle's own fit (whose argmin partition is Table
+    2's for k = 3 and 5): the rescaled weights, factor undone, give Table 2's
+    slice weights to within the fit's distance from the printed 4-decimal
+    constants."""
+    p, c, _ = oracle.fit(k)
+    assert list(p) == GOLD["table2"][str(k)]["p"]
+    r, w, _ = oracle.scale(sigma, p, c)
+    v = w * (2 * r.astype(np.float64) + 1) / np.array(p, dtype=np.float64)
+    assert np.max(np.abs(v / v.sum() - _printed_slices(k))) <= 6e-4
+
+
+def test_scale2_pin_rejects_the_r_for_p_misreading():
+    """Sensitivity of the two pins above: writing r_i for p_i in the area
+    factor of Eq. scale2 (w_i proportional to (c_i - c_{i+1}) r_i / (2 r_i + 1))
+    moves the normalised slice weights by more than 1e-2 at sigma = 2, 8 and
+    13.7 for k = 3 and 5, far outside both tolerances."""
+    for k in (3, 5):
+        row = GOLD["table2"][str(k)]
+        p = np.array(row["p"], dtype=np.float64)
+        c = np.append(np.array(row["c"]), 0.0)
+        for sigma in (2.0, 8.0, 13.7):
+            r = np.floor(sigma * math.pi * p / 100.0 + 1e-9)
+            wm = (c[:-1] - c[1:]) * r / (2 * r + 1)
+            v = wm * (2 * r + 1) / p
+            assert np.max(np.abs(v / v.sum() - _printed_slices(k))) > 1e-2
