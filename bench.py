@@ -170,7 +170,7 @@ def sampled_parity(img, out, dtype, sigma, K, n=300):
         ref = oracle.box_filter_u8_points(im3, b["r"], b["m"], b["G"], ys, xs)
         return bool(np.array_equal(o3[ys, xs, 0], ref))
     ref = oracle.box_filter_points(decode(im3, dtype), b["r"], b["w32"].astype(np.float64), ys, xs)
-    return float(np.max(np.abs(o3[ys, xs, 0].astype(np.float64) - ref)) / np.max(np.abs(im3))) <= 1e-5
+    return float(np.max(np.abs(o3[ys, xs, 0].astype(np.float64) - ref)) / max(np.max(np.abs(ref)), 1e-30)) <= 1e-5
 
 
 # ---------------------------------------------------------------------------

@@ -91,8 +91,8 @@ typedef struct {
     int32_t u8_ok;
 } rsg_boxes;
 
-/* Fit and rescale the boxes for (sigma, K) on the host, in FP64 (the only
- * FP64 computation of the library).  The sigma0 search is exhaustive over all
+/* Fit and rescale the boxes for (sigma, K) on the host, in FP64 (the
+ * kernels compute in FP32 and in integers; FP64 is host-only).  The sigma0 search is exhaustive over all
  * C(100, K) partitions and is cached per K for the life of the process
  * (thread-safe).  sigma must be finite and > 0; K in 1..5.  This is the fit
  * every entry point uses unless the caller passes boxes of its own.
@@ -120,9 +120,14 @@ int rsg_fit_boxes_ex(double sigma, int K, rsg_fit_method method, rsg_boxes* out)
 
 /* Filter one image: rows by the K boxes, then columns (Sections 3.3-3.4), on
  * `stream`: one fused kernel launch, or for wide boxes two launches of a row
- * filter with a transposed store and a stream-ordered intermediate of
- * H*W*C four-byte words (hipMallocAsync / hipFreeAsync on `stream`).  uint8 is computed in exact integers
- * (uint32 running sums, one rounding at the end: round half up of U / G^2);
+ * filter with a transposed store and an intermediate of H*W*C four-byte
+ * words.  That intermediate is the one device allocation of this entry point
+ * (and of rsg_box_filter and rsg_gauss_filter_strided): it is taken and
+ * released in stream order (hipMallocAsync / hipFreeAsync on `stream`),
+ * since the call has no workspace argument; rsg_filter_batch takes it from
+ * the caller's workspace instead.  uint8 is computed in exact integers (uint32 running sums,
+ * a uint64 column combine, one integer rounding at the end: round half up
+ * of U / G^2);
  * FP32 / FP16 / BF16 load as FP32 and accumulate in FP32; FP16 / BF16
  * results are rounded to nearest even.  Row stride = W*C elements.
  * Errors: RSG_EINVAL (NULL pointers, H or W < 1, C not in 1..4, bad dtype,
@@ -186,15 +191,23 @@ typedef struct {
     const rsg_boxes* boxes;   /* NULL: rsg_fit_boxes(sigma, K); else these boxes (read during the call) */
 } rsg_image_desc;
 
-/* Bytes of device workspace rsg_filter_batch needs for these n images.
+/* Bytes of device workspace rsg_filter_batch needs for these n images: the
+ * work list (descriptors, task entries, counters) plus, for every image
+ * planned on the two-pass path, its intermediate of 4 H W C bytes.
  * Errors: as rsg_gauss_filter for any descriptor, RSG_EINVAL (n < 1). */
 int rsg_filter_batch_workspace(const rsg_image_desc* d, int n, size_t* bytes);
 
-/* Filter n images of mixed size, channel count, dtype and sigma in ONE
- * persistent kernel launch on `stream`.  The caller provides a device
- * workspace of at least rsg_filter_batch_workspace() bytes (descriptors and
- * the work list are copied into it asynchronously on `stream`, so the
- * workspace must not be reused until the stream has passed this call).
+/* Filter n images of mixed size, channel count, dtype and sigma on
+ * `stream`: one persistent launch per kernel class among the images planned
+ * on the fused path (element type x channel count x tap count: a single
+ * launch when the images share one), whose workgroups pop (image, task)
+ * pairs from a shared counter, then for the images planned on the two-pass
+ * path one launch per pass and pass instantiation.  The caller provides a
+ * device workspace of at least rsg_filter_batch_workspace() bytes: the work
+ * list is copied into it asynchronously on `stream` and the two-pass
+ * intermediates are carved from it, so the workspace must not be reused
+ * until the stream has passed this call.  The call allocates no device
+ * memory.
  * Each image's result is bit-identical to rsg_gauss_filter on that image
  * alone: float images keep their single-image tile plan; uint8 images may
  * get longer segments in a batch (fewer halo rows), which cannot change
@@ -209,9 +222,11 @@ int rsg_filter_batch(const rsg_image_desc* d, int n, void* d_workspace, size_t w
 typedef struct rsg_server rsg_server;
 
 /* d_arena / arena_bytes: caller-owned device memory the server carves its
- * per-launch workspaces from.  hbm_budget: admission limit on the sum of the
- * in-flight requests' device bytes (src + dst, plus the intermediate of
- * requests planned on the two-pass path); 0 means unlimited.
+ * per-launch workspaces from: max_inflight equal slots, each holding one
+ * launch's work list and the intermediates of its two-pass requests (the
+ * server allocates no device memory).  hbm_budget: admission limit on the
+ * sum of the in-flight requests' image bytes (src + dst); 0 means
+ * unlimited.
  * max_inflight: launches outstanding at once (1..64); n_streams: HIP streams
  * the server creates (1..8); queue_depth: requests waiting for admission
  * (>= 1); max_batch: requests per launch (>= 1). */
@@ -230,11 +245,14 @@ typedef struct {
 int rsg_server_create(const rsg_server_config* cfg, rsg_server** out);
 
 /* Queue one request (device-resident src/dst, as rsg_image_desc); never
- * blocks.  Requests are admitted in arrival order when the HBM budget and an
- * in-flight slot allow, and batched with whatever else is waiting into one
- * persistent launch while earlier launches are still running.
+ * blocks (the scheduler plans and launches outside the server lock).
+ * Requests are admitted in arrival order when the HBM budget, a free
+ * in-flight slot and that slot's workspace allow, and batched with whatever
+ * else is waiting into one batched launch (as rsg_filter_batch) while
+ * earlier launches are still running on other slots and streams.
  * Errors: RSG_EINVAL (bad descriptor), RSG_ENOMEM (the request alone exceeds
- * the HBM budget or the arena), RSG_EBUSY (queue full). */
+ * the HBM budget, or its work list and intermediate exceed an arena slot),
+ * RSG_EBUSY (queue full). */
 int rsg_submit(rsg_server* s, const rsg_image_desc* req, uint64_t* ticket);
 
 /* Timestamps are CLOCK_MONOTONIC nanoseconds. */
@@ -280,14 +298,16 @@ int rsg_tune_override(int32_t seg_height);
 
 /* Process-wide choice of kernel path for every later plan: 0 lets the
  * planner choose (the tuning table, else two passes for wide boxes,
- * R * C >= 40, when they fit), 1 forces the fused single-launch kernel (two
- * waves per task: row pass and column pass), 2 forces the two-pass path (row
- * filter into an FP32 / uint32 intermediate stored transposed, then the same
- * on the intermediate; the intermediate, 4 H W C bytes, is allocated and
- * released in stream order), 3 forces the fused kernel with one wave per
- * task (software-pipelined; batches planned under it use the one-wave batch
- * kernel too).  The fused forms give identical bits; results of the fused
- * and two-pass paths agree to FP32 rounding and are bit-identical for uint8.  For the autotuner and tests.
+ * R * C >= 40, when they fit), 1 forces the fused single-launch kernel
+ * (workgroups of four waves per task, each wave running both passes on its
+ * block of every step of rows), 2 forces the two-pass path (row filter into
+ * an FP32 / uint32 intermediate stored transposed, then the same on the
+ * intermediate; the intermediate, 4 H W C bytes, comes from where the entry
+ * point takes it), 3 forces the fused kernel with one wave per task
+ * (software-pipelined; batches planned under it use the one-wave batch
+ * kernel too).  Results of the fused forms and of the two-pass path agree to
+ * FP32 rounding and are bit-identical for uint8.  For the autotuner and
+ * tests.
  * Errors: RSG_EINVAL (path not in 0..3); later plans return
  * RSG_EUNSUPPORTED when the forced path cannot hold the boxes. */
 int rsg_tune_path(int32_t path);

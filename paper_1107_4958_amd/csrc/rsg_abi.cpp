@@ -204,7 +204,7 @@ int rsg_filter_batch_workspace(const rsg_image_desc* d, int n, size_t* bytes)
     std::vector<rsg::BatchTask> tasks;
     int rc = rsg::plan_batch(d, n, imgs, tasks);
     if (rc != RSG_OK) return rc;
-    *bytes = rsg::batch_workspace_bytes(n, int(int64_t(tasks.size()) + rsg::pass_blocks(imgs.data(), n)));
+    *bytes = rsg::batch_workspace_bytes(imgs.data(), n, int64_t(tasks.size()) + rsg::pass_blocks(imgs.data(), n));
     return RSG_OK;
 }
 

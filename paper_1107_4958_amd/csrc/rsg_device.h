@@ -3,36 +3,38 @@
 // A task is a strip of 64 consecutive sample-columns (lane c owns column
 // s0 + c in the column pass) and a segment of hs output rows of one image.
 // It streams down the image in groups of G input rows, either on one wave
-// (both passes, software-pipelined: stream_task) or on a workgroup whose
-// row-pass and column-pass waves hand each group over through LDS
-// (stream_task_pc, the default):
+// (both passes, software-pipelined: stream_task) or on a workgroup of
+// kCoWaves waves that split every step of rows between them, each running
+// both passes on its own block and exchanging the column sums' carries
+// through LDS (stream_task_co, the default):
 //
-//   row pass (Section 3.3, Eq. alg1 / indep, along x): the row-pass wave splits into
-//     G = 64 / SEG segments of SEG lanes; segment j takes input row
-//     (group start + j), lane q of the segment holds NPL consecutive samples
-//     of the row span [s0 - (R+1)C, s0 + 64 + RC) (border samples replicated,
-//     reflected or zero).  The running sum I of each row is a serial scan inside the
-//     lane plus a DPP scan of the lane totals across the segment; the G rows
-//     of running sums go to LDS.  Then every lane (now: a column) takes
+//   row pass (Section 3.3, Eq. alg1 / indep, along x): the wave splits into
+//     G = 64 / SEG segments of SEG lanes; segment j takes one input row,
+//     lane q of the segment holds NPL consecutive samples of the row span
+//     [s0 - (R+1)C, s0 + 64 + RC) (border samples replicated, reflected or
+//     zero).  The running sum I of each row is a serial scan inside the lane
+//     plus a DPP scan of the lane totals across the segment; the G rows of
+//     running sums go to LDS.  Then every lane (now: a column) takes
 //     T(s) = sum_k w_k (I(s + r_k C) - I(s - (r_k+1) C)) for each row.
-//   column pass (Section 3.4, the same along y): each lane adds T to its
-//     running column sum J, writes J to an LDS ring holding the last
-//     L >= 2R + 1 + G rows and emits, for the row R behind the newest,
-//     out = sum_k w_k (J(y + r_k) - J(y - r_k - 1)).
+//   column pass (Section 3.4, the same along y): running column sums J of T
+//     in an LDS ring holding at least the last 2R + 2 rows, and for the row R
+//     behind each summed row out = sum_k w_k (J(y + r_k) - J(y - r_k - 1)).
 //
 // Global memory is addressed through buffer descriptors with row offsets in
 // SGPRs: border zero-padding and dropped stores (rows outside the task, lanes
 // past the image) use an out-of-range offset instead of branches, so every
-// group issues a fixed number of memory instructions and the next groups'
+// step issues a fixed number of memory instructions and the next steps'
 // loads stay in flight while the current one is processed.
 //
 // FP32 / FP16 / BF16 accumulate in FP32.  Running sums are tile-local and
 // offset: each group of rows subtracts one of its samples (added back
-// through the DC gain of the boxes) and each column its first T value, which
-// keeps the summed magnitudes, and hence the rounding of the differences,
-// small.  Both forms perform the same FP32 operations in the same order.
-// uint8 uses exact uint32 arithmetic (differences are exact modulo 2^32 and
-// every box sum is < 2^32), integer weights m_k and one exact rounding of
+// through the DC gain of the boxes) and each column a constant of its own,
+// which keeps the summed magnitudes, and hence the rounding of the
+// differences, small.  Zero extension takes no offsets: outside samples must
+// enter the sums as 0, or a box lying mostly outside the image would be a
+// small difference of large sums.  uint8 uses exact uint32 arithmetic
+// (differences are exact modulo 2^32 and every box sum is < 2^32), integer
+// weights m_k, a uint64 column combine and one exact integer rounding of
 // U / G^2.
 //
 // There is no MFMA: the method costs 4K additions and 2K multiplications per
@@ -210,33 +212,26 @@ __device__ __forceinline__ void load_chunk_elem(Chunk<Tr, NPL>& ch, __amdgpu_buf
     }
 }
 
-// uint8 output: round half up of U / G^2, exactly.  N = U + floor(G^2/2) < 256 G^2.
+// uint8 output: round half up of U / G^2, exactly, in integer arithmetic.
+// N = U + floor(G^2 / 2) < 256 G^2 <= 2^56.  The FP32 estimate of N / G^2
+// (N's high word is exact in FP32; three roundings of 2^-24 each keep it
+// within 2^-13 of the quotient, which is below 256), lowered by a margin of
+// 2^-11, truncates to q or q - 1; one 64-bit remainder in [0, 2 G^2)
+// decides.  G^2 < 2^48, so q G^2 needs one 32 x 32 -> 64 product and one
+// 24-bit product for its high word.
 __device__ __forceinline__ uint32_t exact_round_div_u(uint64_t U, uint64_t G2, uint64_t G2half, float invG2)
 {
     const uint64_t N = U + G2half;
-    const float nf = float(uint32_t(N >> 32)) * 4294967296.0f + float(uint32_t(N));
-    uint32_t q = uint32_t(nf * invG2);
-    const uint64_t prod = uint64_t(q) * G2;
-    if (prod > N) q -= 1;
-    else if (N - prod >= G2) q += 1;
-    return q;
+    const float nf = fmaf(float(uint32_t(N >> 32)), 4294967296.0f, float(uint32_t(N)));
+    uint32_t q = uint32_t(fmaxf(fmaf(nf, invG2, -0.00048828125f), 0.0f));
+    uint64_t P = uint64_t(q) * uint64_t(uint32_t(G2));
+    P += uint64_t(__umul24(q, uint32_t(G2 >> 32))) << 32;
+    const uint64_t r = N - P;
+    return q + ((r >= G2) ? 1u : 0u);
 }
 __device__ __forceinline__ uint32_t exact_round_div(uint64_t U, const ImgParams& ip)
 {
     return exact_round_div_u(U, ip.G2, ip.G2half, ip.invG2);
-}
-
-// The same in FP64 for U < 2^53 given exactly as a double (sum of FP64
-// products that are all exact): quotient estimate from the reciprocal, then
-// one exact remainder N - q G^2 (an FMA) decides a +-1 correction.
-__device__ __forceinline__ uint32_t exact_round_div_f64(double U, double G2, double G2half, double invG2)
-{
-    const double N = U + G2half;                       // exact: < 2^53
-    double q = floor(N * invG2);
-    const double r = fma(-q, G2, N);                   // exact remainder
-    q += (r >= G2) ? 1.0 : 0.0;
-    q -= (r < 0.0) ? 1.0 : 0.0;
-    return uint32_t(q);
 }
 
 // One element at byte offset `boff` of a buffer, as float.
@@ -302,7 +297,6 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     using Acc = typename Tr::Acc;
     constexpr bool kInt = Tr::kInt;
     constexpr int G = kWave / SEG;             // rows per group
-    constexpr int PW = SEG * NPL;              // span capacity
     constexpr int PP = row_tile_pitch(SEG, NPL);   // LDS pitch of the row-sum tile
     constexpr int RP = kWave;                      // LDS pitch of the column ring
     constexpr int PF = kPrefetch;
@@ -419,7 +413,8 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         Acc v[NPL];
         float off = 0.0f;
         if constexpr (!kInt) {
-            off = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(bf.w, 0))));
+            off = (boundary == RSG_ZERO) ? 0.0f
+                                         : __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(bf.w, 0))));
 #pragma unroll
             for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(bf.w, i) - off;
         } else {
@@ -532,14 +527,11 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         for (int j = 0; j < G; ++j) {
             const int voff = int(og + uint32_t(j) * dstr);
             if constexpr (kInt) {
-                // U = sum m_k D_k < 2^52: every product and partial sum is an
-                // exact FP64 value, and FP64 FMAs run at the FP32 rate here
-                double U = 0.0;
+                // U = sum m_k D_k < 256 G^2: exact in uint64
+                uint64_t U = 0;
 #pragma unroll
-                for (int k = 0; k < KT; ++k)
-                    U = fma(double(wm[k]), double(uint32_t(rv[j][2 * k] - rv[j][2 * k + 1])), U);
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div_f64(U, ip.G2d, ip.G2halfd, ip.invG2d)),
-                                                     rs_dst, voff, 0, 0);
+                for (int k = 0; k < KT; ++k) U += uint64_t(wm[k]) * uint64_t(rv[j][2 * k] - rv[j][2 * k + 1]);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, voff, 0, 0);
             } else {
                 float o = c2dc;
 #pragma unroll
@@ -579,7 +571,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         if constexpr (!kInt) init = off_cur * dc;
         row_combine(pv, T, init);
         if constexpr (!kInt) {
-            c2 = T[0];                                  // the column offset: the task's first row
+            c2 = (boundary == RSG_ZERO) ? 0.0f : T[0];  // the column offset: the task's first row
             c2dc = c2 * dc;
         }
         dropped_stores(PF * G + G);
@@ -616,22 +608,38 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 }
 
 // --------------------------------------------------------------------------
-// Producer / consumer form of the streaming loop: one task per workgroup of
-// kProducers + 1 waves.  The row pass is independent from row to row, so
-// waves 0 .. NPR-1 each run it for every NPR-th group (loads, running sums,
-// row box differences) and hand the group's row results to the last wave
-// through an LDS queue; that wave runs the column pass of the groups in
-// order (running column sums in the ring, column box differences, stores).
-// Step s covers groups s NPR .. s NPR + NPR - 1 and ends, for the row-pass
-// waves, in one workgroup barrier: at barrier s queue slot s & 1 holds the
-// step's groups, and the slot the row-pass waves fill next was read by the
-// column-pass wave before it reached barrier s.  Every wave takes the same
-// number of barriers.  The split multiplies the waves per task without
-// adding halo rows, and each wave's chain of dependent LDS round trips is a
-// fraction of the one-wave form's.
+// Cooperative form of the streaming loop: one task per workgroup of
+// kCoWaves waves that share the strip.  Step m covers iterations
+// [m MB, (m + 1) MB), MB = kCoWaves * kCoRows; wave w takes the block of
+// kCoRows iterations starting at m MB + w kCoRows and runs both passes on it:
+//
+//   row pass    its groups of G rows (loads prefetched two groups ahead in
+//               the wave's own sequence, running sums, row tile, Eq. indep
+//               along x) -> T of its kCoRows rows in registers;
+//   column sums the block's running sums of T (Eq. alg1 down the column,
+//               in registers), its total to LDS; barrier; the block's carry
+//               (sum of the earlier blocks' totals, added in the same order
+//               by every wave) makes them the strip's running sums, written
+//               to the LDS ring; barrier;
+//   column out  K box differences down the column (Eq. indep) for the
+//               block's rows, read from the ring, and one store per row.
+//
+// The ring holds L >= MB + 2R + 1 rows (a multiple of kCoRows) plus kCoRows
+// mirror rows, so the taps of a block are read at (per-block slot) + row
+// without a modulo.  Two barriers per step of MB rows, all waves doing the
+// same work, several steps of loads in flight: the strip streams without a
+// serial chain of LDS round trips per row.  Float columns sum T - c with c a
+// per-column constant (the input sample at the task's first row), restored
+// through the DC gain of the boxes, so the sums stay at the size of local
+// variations (c = 0 under zero extension).
+//
+// Iteration `it` reads input row ybase + it and, for it >= 2R + 1, emits
+// output row ybase + it - R.  Rows past the task are stored to dropped
+// offsets, so every step issues the same memory operations and the waits
+// for the prefetched loads stay exact.
 // --------------------------------------------------------------------------
-template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE>
-__device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
+template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE, int NW_ = kCoWaves, int RB_ = kCoRows>
+__device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
 {
     using Acc = typename Tr::Acc;
     constexpr bool kInt = Tr::kInt;
@@ -639,27 +647,28 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
     constexpr int PW = SEG * NPL;
     constexpr int PP = row_tile_pitch(SEG, NPL);
     constexpr int RP = kWave;
-    constexpr int PF = kPrefetch;
+    constexpr int NW = NW_;                    // waves per task
+    constexpr int RB = RB_;                    // rows per wave per step
+    constexpr int NGW = RB / G;                // row groups per wave per step
+    constexpr int MB = NW * RB;                // rows per step
+    constexpr int PF = 2;                      // groups of loads in flight per wave
+    static_assert(RB % G == 0 && NGW % PF == 0, "a step holds whole groups and whole prefetch rounds");
+    static_assert(PW <= PP, "tile pitch");
     constexpr int es = Tr::kSize;
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);   // uniform: scalar slot arithmetic
     const int lane = threadIdx.x % kWave;
     const int R = ip.R;
-    const int L = ip.L;
+    const int L = ip.Lco;
     const int H = ip.H;
     const int W = ip.W;
     const int WC = W * C;
     const int boundary = ip.boundary;
-    static_assert(PW <= PP, "tile pitch");
 
-    constexpr int NPR = kProducers;
-    // LDS: [row tiles NPR x G x PP][queue 2 x NPR x G x 64][ring (L + G) x 64]
-    Acc* P = reinterpret_cast<Acc*>(lds);
-    Acc* Q = P + NPR * G * PP;
-    Acc* ring = Q + 2 * NPR * G * kWave;
+    // LDS: [row tiles NW x G x PP][block totals NW x 64][ring (L + RB) x 64]
+    Acc* Pt = reinterpret_cast<Acc*>(lds) + wave * G * PP;
+    Acc* X = reinterpret_cast<Acc*>(lds) + NW * G * PP;
+    Acc* ring = X + NW * kWave;
 
-    const int ngroups = (tg.niter + G - 1) / G;
-    // steps of NPR groups, a multiple of PF; every wave: one barrier per step
-    const int nsteps = (ngroups + NPR * PF - 1) / (NPR * PF) * PF;
     const float dc = ip.dc32;
     float wf[KT];
     uint32_t wm[KT];
@@ -670,242 +679,305 @@ __device__ __forceinline__ void stream_task_pc(const ImgParams& ip, const TaskGe
     }
     const int64_t sstride = ip.src_stride * es;
     const int64_t dstride = ip.dst_stride * es;
+    const int nsteps = (tg.niter + MB - 1) / MB;
 
-    if (wave < NPR) {
-        // ---------------- row pass of groups wave, wave + NPR, ... ----------------
-        Acc* Pt = P + wave * G * PP;
-        const int jrow = lane / SEG;
-        const int q = lane % SEG;
-        const int y_lo = max(0, tg.ybase);
-        const char* sbase = reinterpret_cast<const char*>(ip.src) + tg.slice_off + int64_t(y_lo) * sstride;
-        const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(H - 1 - y_lo) * sstride + int64_t(WC) * es);
-        const int cs = tg.a0 + NPL * q;
-        const int vec_voff = cs * es;
-        int eoff[EDGE ? NPL : 1];
-        if constexpr (EDGE) {
-            const int x0 = floor_div(cs, C);
+    // ---------------- row-pass setup ----------------
+    const int jrow = lane / SEG;
+    const int q = lane % SEG;
+    const int y_lo = max(0, tg.ybase);
+    const char* sbase = reinterpret_cast<const char*>(ip.src) + tg.slice_off + int64_t(y_lo) * sstride;
+    const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(H - 1 - y_lo) * sstride + int64_t(WC) * es);
+    const int cs = tg.a0 + NPL * q;
+    const int vec_voff = cs * es;
+    int eoff[EDGE ? NPL : 1];
+    if constexpr (EDGE) {
+        const int x0 = floor_div(cs, C);
 #pragma unroll
-            for (int i = 0; i < NPL; ++i) {
-                const int x = x0 + i / C;
-                const int xe = ext_index(x, W, boundary);
-                eoff[i] = (xe >= 0) ? (xe * C + i % C) * es : -1;
-            }
+        for (int i = 0; i < NPL; ++i) {
+            const int x = x0 + i / C;
+            const int xe = ext_index(x, W, boundary);
+            eoff[i] = (xe >= 0) ? (xe * C + i % C) * es : -1;
         }
-        const int sstride32 = int(sstride);
-        // 4-byte samples on a border task: a lane whose chunk lies inside the
-        // row loads it as vectors, the others per element; each lane's other
-        // load reads out of range (zeros), and the two are ORed when the group
-        // is used, so no branch diverges and every wait stays exact
-        constexpr bool kSplit = EDGE && Tr::kSize == 4;
-        const bool lane_vec = ip.vec && cs >= 0 && cs + NPL <= WC;
-        auto load = [&](Chunk<Tr, NPL>& ch, Chunk<Tr, NPL>& ech, int st) {    // the group of step st
-            const int y = tg.ybase + (st * NPR + wave) * G + jrow;
-            const int ye = ext_index(y, H, boundary);
-            const bool zero_row = ye < 0;
-            const int rowoff = (zero_row ? 0 : ye - y_lo) * sstride32;
+    }
+    const int sstride32 = int(sstride);
+    // 4-byte samples on a border task: a lane whose chunk lies inside the row
+    // loads it as vectors, the others per element; each lane's other load
+    // reads out of range (zeros), and the two are ORed when the group is
+    // used, so no branch diverges and every wait stays exact
+    constexpr bool kSplit = EDGE && Tr::kSize == 4;
+    const bool lane_vec = ip.vec && cs >= 0 && cs + NPL <= WC;
+    // Offsets of a group whose rows all lie in [y_lo, H): this lane's row
+    // within the group and column in VGPRs (fixed for the task), the group's
+    // first row in the scalar offset.  Other groups extend each lane's row.
+    const int jrow_off = jrow * sstride32;
+    const int fast_vec = (kSplit ? lane_vec : true) ? vec_voff + jrow_off : kDropOffset;
+    int fast_elem[EDGE ? NPL : 1];
+    if constexpr (EDGE) {
+#pragma unroll
+        for (int i = 0; i < NPL; ++i)
+            fast_elem[i] = ((kSplit && lane_vec) || eoff[i] < 0) ? kDropOffset : eoff[i] + jrow_off;
+    }
+    // group gq of this wave: iterations (gq / NGW) MB + wave RB + (gq % NGW) G + [0, G)
+    auto load = [&](Chunk<Tr, NPL>& ch, Chunk<Tr, NPL>& ech, int gq) {
+        const int it = (gq / NGW) * MB + wave * RB + (gq % NGW) * G;
+        const int yg = tg.ybase + it;
+        if (yg >= y_lo && yg + G <= H) {
+            const int soff = (yg - y_lo) * sstride32;
             if constexpr (kSplit) {
-                load_chunk_vec<Tr, NPL>(ch, rs_src, (lane_vec && !zero_row) ? vec_voff + rowoff : kDropOffset, 0);
-                int vo[NPL];
-#pragma unroll
-                for (int i = 0; i < NPL; ++i)
-                    vo[i] = (lane_vec || eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
-                load_chunk_elem<Tr, NPL>(ech, rs_src, vo, 0);
+                load_chunk_vec<Tr, NPL>(ch, rs_src, fast_vec, soff);
+                load_chunk_elem<Tr, NPL>(ech, rs_src, fast_elem, soff);
             } else if constexpr (EDGE) {
-                int vo[NPL];
-#pragma unroll
-                for (int i = 0; i < NPL; ++i) vo[i] = (eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
-                load_chunk_elem<Tr, NPL>(ch, rs_src, vo, 0);
+                load_chunk_elem<Tr, NPL>(ch, rs_src, fast_elem, soff);
             } else {
-                load_chunk_vec<Tr, NPL>(ch, rs_src, zero_row ? kDropOffset : vec_voff + rowoff, 0);
+                load_chunk_vec<Tr, NPL>(ch, rs_src, fast_vec, soff);
             }
-        };
-        int tp[KT], tm[KT];
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            tp[k] = tg.off + lane + ip.r[k] * C;
-            tm[k] = tg.off + lane - (ip.r[k] + 1) * C;
+            return;
         }
-        Chunk<Tr, NPL> buf[PF];
-        Chunk<Tr, NPL> ebuf[kSplit ? PF : 1];
+        const int y = yg + jrow;
+        const int ye = ext_index(y, H, boundary);
+        const bool zero_row = ye < 0;
+        const int rowoff = (zero_row ? 0 : ye - y_lo) * sstride32;
+        if constexpr (kSplit) {
+            load_chunk_vec<Tr, NPL>(ch, rs_src, (lane_vec && !zero_row) ? vec_voff + rowoff : kDropOffset, 0);
+            int vo[NPL];
 #pragma unroll
-        for (int b = 0; b < PF; ++b) {          // this wave issues loads only: every wait is exact
-            __builtin_amdgcn_sched_barrier(0);
-            load(buf[b], ebuf[kSplit ? b : 0], b);
+            for (int i = 0; i < NPL; ++i)
+                vo[i] = (lane_vec || eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
+            load_chunk_elem<Tr, NPL>(ech, rs_src, vo, 0);
+        } else if constexpr (EDGE) {
+            int vo[NPL];
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) vo[i] = (eoff[i] < 0 || zero_row) ? kDropOffset : eoff[i] + rowoff;
+            load_chunk_elem<Tr, NPL>(ch, rs_src, vo, 0);
+        } else {
+            load_chunk_vec<Tr, NPL>(ch, rs_src, zero_row ? kDropOffset : vec_voff + rowoff, 0);
         }
+    };
+    int tp[KT], tm[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        tp[k] = tg.off + lane + ip.r[k] * C;
+        tm[k] = tg.off + lane - (ip.r[k] + 1) * C;
+    }
+
+    // ---------------- column setup ----------------
+    // Output rows of this task: y0 .. y0 + hs - 1, or with a strided output
+    // (every ostep-th row and pixel, compacted) the kept rows oq0 .. oq1 - 1
+    // of the output image; rows outside the descriptor and dropped columns
+    // are stored to out-of-range offsets.
+    const int ostep = ip.step > 1 ? ip.step : 1;
+    const int s = tg.s0 + lane;
+    int oq0 = tg.y0, nrows = tg.hs, orow_len = WC;
+    uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
+    if (ostep > 1) {
+        oq0 = (tg.y0 + ostep - 1) / ostep;
+        nrows = (tg.y0 + tg.hs - 1) / ostep - oq0 + 1;
+        orow_len = (W + ostep - 1) / ostep * C;
+        const int x = s / C;
+        ocol = (s < WC && x % ostep == 0) ? uint32_t(((x / ostep) * C + (s - x * C)) * es) : kDropColumn;
+    }
+    const char* dbase = reinterpret_cast<char*>(ip.dst) + tg.slice_off + int64_t(oq0) * dstride;
+    const __amdgpu_buffer_rsrc_t rs_dst =
+        make_rsrc(dbase, nrows > 0 ? int64_t(nrows - 1) * dstride + int64_t(orow_len) * es : 0);
+    const uint32_t dstr = uint32_t(dstride);
+    // column offset (float types): the input sample at the task's first row
+    float cf = 0.0f;
+    if constexpr (!kInt) {
+        if (boundary != RSG_ZERO) {
+            const int yc = ext_index(tg.ybase, H, boundary);     // >= y_lo
+            cf = Tr_load_one<Tr>(rs_src, (yc - y_lo) * sstride32 + min(s, WC - 1) * es);
+        }
+    }
+    const float cdc = cf * dc;
+
+    auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, 0);
+            else store_out<Tr>(rs_dst, kDropOffset - 64 * (base + j), 0, 0.0f);
+        }
+    };
+
+    // Prologue: the first PF groups' loads and RB dropped stores, the memory
+    // operations that precede the loop's first wait as they precede it
+    // around the back edge.
+    Chunk<Tr, NPL> buf[PF];
+    Chunk<Tr, NPL> ebuf[kSplit ? PF : 1];
+#pragma unroll
+    for (int b = 0; b < PF; ++b) {
         __builtin_amdgcn_sched_barrier(0);
-        for (int g = 0; g < nsteps; g += PF) {
+        load(buf[b], ebuf[kSplit ? b : 0], b);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    dropped_stores(0);
+    __builtin_amdgcn_sched_barrier(0);
+
+    Acc carry = Acc(0);
+    int slot_m = 0;                            // ring slot of iteration m MB
+    for (int m = 0; m < nsteps; ++m) {
+        Acc T[RB];
 #pragma unroll
-            for (int b = 0; b < PF; ++b) {
-                const int gg = g + b;
-                __builtin_amdgcn_sched_barrier(0);
-                if constexpr (kSplit) {
+        for (int g = 0; g < NGW; ++g) {
+            const int b = g % PF;
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (kSplit) {
 #pragma unroll
-                    for (int k = 0; k < Chunk<Tr, NPL>::kWords; ++k) buf[b].w[k] |= ebuf[b].w[k];
-                }
-                Acc v[NPL];
-                float off = 0.0f;
-                if constexpr (!kInt) {
-                    off = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(buf[b].w, 0))));
-#pragma unroll
-                    for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i) - off;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                load(buf[b], ebuf[kSplit ? b : 0], gg + PF);
-                __builtin_amdgcn_sched_barrier(0);
-                // running sums along the row (Eq. alg1)
-#pragma unroll
-                for (int i = C; i < NPL; ++i) v[i] = v[i] + v[i - C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const Acc tot = v[NPL - C + c];
-                    const Acc ex = segment_inclusive_scan<SEG>(tot) - tot;
-#pragma unroll
-                    for (int i = c; i < NPL; i += C) v[i] = v[i] + ex;
-                }
-                using Acc4 = typename std::conditional<kInt, uint4, float4>::type;
-                Acc4* dst4 = reinterpret_cast<Acc4*>(Pt + jrow * PP + q * NPL);
-#pragma unroll
-                for (int h = 0; h < NPL / 4; ++h) {
-                    Acc4 t4;
-                    t4.x = v[4 * h]; t4.y = v[4 * h + 1]; t4.z = v[4 * h + 2]; t4.w = v[4 * h + 3];
-                    dst4[h] = t4;
-                }
-                wave_lds_fence();
-                // row box differences (Eq. indep), lane = column; floats add
-                // the group offset's share
-                float init = 0.0f;
-                if constexpr (!kInt) init = off * dc;
-                Acc T[G];
-#pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    const Acc* Pj = Pt + j * PP;
-                    Acc t;
-                    if constexpr (kInt) {
-                        t = 0;
-#pragma unroll
-                        for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
-                    } else {
-                        t = fmaf(wf[0], Pj[tp[0]] - Pj[tm[0]], init);
-#pragma unroll
-                        for (int k = 1; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
-                    }
-                    T[j] = t;
-                }
-                Acc* Qs = Q + ((gg & 1) * NPR + wave) * G * kWave;
-#pragma unroll
-                for (int j = 0; j < G; ++j) Qs[j * kWave + lane] = T[j];
-                __syncthreads();
+                for (int k = 0; k < Chunk<Tr, NPL>::kWords; ++k) buf[b].w[k] |= ebuf[b].w[k];
             }
-        }
-    } else {
-        // ---------------- column pass ----------------
-        // Output rows of this task: y0 .. y0 + hs - 1, or with a strided
-        // output (every ostep-th row and pixel, compacted) the kept rows
-        // oq0 .. oq1 - 1 of the output image; rows outside the descriptor
-        // and dropped columns are stored to out-of-range offsets.
-        const int ostep = ip.step > 1 ? ip.step : 1;
-        const int s = tg.s0 + lane;
-        int oq0 = tg.y0, nrows = tg.hs, orow_len = WC;
-        uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
-        if (ostep > 1) {
-            oq0 = (tg.y0 + ostep - 1) / ostep;
-            nrows = (tg.y0 + tg.hs - 1) / ostep - oq0 + 1;
-            orow_len = (W + ostep - 1) / ostep * C;
-            const int x = s / C;
-            ocol = (s < WC && x % ostep == 0) ? uint32_t(((x / ostep) * C + (s - x * C)) * es) : kDropColumn;
-        }
-        const char* dbase = reinterpret_cast<char*>(ip.dst) + tg.slice_off + int64_t(oq0) * dstride;
-        const __amdgpu_buffer_rsrc_t rs_dst =
-            make_rsrc(dbase, nrows > 0 ? int64_t(nrows - 1) * dstride + int64_t(orow_len) * es : 0);
-        const uint32_t dstr = uint32_t(dstride);
-        Acc colacc = Acc(0);
-        float c2 = 0.0f;
-        float c2dc = 0.0f;
-        int slot0 = 0;
-        for (int st = 0; st < nsteps; ++st) {
-            __syncthreads();
-#pragma unroll 1
-          for (int pq = 0; pq < NPR; ++pq) {
-            const int g = st * NPR + pq;
-            const Acc* Qs = Q + ((st & 1) * NPR + pq) * G * kWave;
+            Acc v[NPL];
+            float off = 0.0f;
             if constexpr (!kInt) {
-                if (g == 0) {                    // the column offset: the task's first row
-                    c2 = Qs[lane];
-                    c2dc = c2 * dc;
-                }
-            }
-            const int wbase = slot0 * RP + lane;
-            Acc cj[G];
+                off = (boundary == RSG_ZERO)
+                          ? 0.0f
+                          : __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(buf[b].w, 0))));
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                if constexpr (kInt) colacc += Qs[j * kWave + lane];
-                else colacc += Qs[j * kWave + lane] - c2;
-                cj[j] = colacc;
-                ring[wbase + j * RP] = colacc;
-            }
-            if (slot0 == 0) {                       // slots 0 .. G-1 also live at L .. L+G-1
+                for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i) - off;
+            } else {
 #pragma unroll
-                for (int j = 0; j < G; ++j) ring[(L + j) * RP + lane] = cj[j];
+                for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            load(buf[b], ebuf[kSplit ? b : 0], m * NGW + g + PF);
+            __builtin_amdgcn_sched_barrier(0);
+            // running sums along the row (Eq. alg1)
+#pragma unroll
+            for (int i = C; i < NPL; ++i) v[i] = v[i] + v[i - C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const Acc tot = v[NPL - C + c];
+                const Acc ex = segment_inclusive_scan<SEG>(tot) - tot;
+#pragma unroll
+                for (int i = c; i < NPL; i += C) v[i] = v[i] + ex;
+            }
+            using Acc4 = typename std::conditional<kInt, uint4, float4>::type;
+            Acc4* dst4 = reinterpret_cast<Acc4*>(Pt + jrow * PP + q * NPL);
+#pragma unroll
+            for (int h = 0; h < NPL / 4; ++h) {
+                Acc4 t4;
+                t4.x = v[4 * h]; t4.y = v[4 * h + 1]; t4.z = v[4 * h + 2]; t4.w = v[4 * h + 3];
+                dst4[h] = t4;
             }
             wave_lds_fence();
-            Acc rv[G][2 * KT];
+            // row box differences (Eq. indep), lane = column; floats add the
+            // group offset's share
+            float init = 0.0f;
+            if constexpr (!kInt) init = off * dc;
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const Acc* Pj = Pt + j * PP;
+                Acc t;
+                if constexpr (kInt) {
+                    t = 0;
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
+                } else {
+                    t = fmaf(wf[0], Pj[tp[0]] - Pj[tm[0]], init);
+#pragma unroll
+                    for (int k = 1; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
+                }
+                T[g * G + j] = t;
+            }
+        }
+
+        // ---- column running sums of the block (Eq. alg1), then its carry ----
+        {   // T becomes the block's running sums J
+            Acc run = Acc(0);
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                if constexpr (kInt) run += T[i];
+                else run += T[i] - cf;
+                T[i] = run;
+            }
+            X[wave * kWave + lane] = run;
+        }
+        __syncthreads();
+        Acc cw = carry;
+        {
+            Acc acc = carry;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) {
+                cw = (v == wave) ? acc : cw;
+                acc += X[v * kWave + lane];
+            }
+            carry = acc;
+        }
+        int sb = slot_m + wave * RB;
+        sb -= (sb >= L) ? L : 0;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            T[i] = cw + T[i];
+            ring[(sb + i) * RP + lane] = T[i];
+        }
+        if (sb == 0) {                         // slots 0 .. RB-1 also live at L .. L+RB-1
+#pragma unroll
+            for (int i = 0; i < RB; ++i) ring[(L + i) * RP + lane] = T[i];
+        }
+        __syncthreads();
+
+        // ---- column box differences (Eq. indep) and stores, in two halves
+        //      of the block (fewer taps live at once) ----
+        int ta[KT], tb[KT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            ta[k] = sb - R + ip.r[k];
+            tb[k] = sb - R - ip.r[k] - 1;
+            ta[k] += (ta[k] < 0) ? L : 0;
+            tb[k] += (tb[k] < 0) ? L : 0;
+        }
+        // output row of block row i: k = (first iteration of the block) + i - (2R + 1)
+        const int kb = m * MB + wave * RB - tg.emit0;
+        int qrow = 0, rr = 0;
+        if (ostep > 1) {
+            const int yb = tg.y0 + kb;
+            qrow = floor_div(yb, ostep);
+            rr = yb - qrow * ostep;
+        }
+        constexpr int HB = RB / 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __builtin_amdgcn_sched_barrier(0);
+            Acc rv[HB][2 * KT];
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
-                int a = slot0 - R + ip.r[k];
-                int b = slot0 - R - ip.r[k] - 1;
-                a += (a < 0) ? L : 0;
-                b += (b < 0) ? L : 0;
 #pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    rv[j][2 * k] = ring[a * RP + lane + j * RP];
-                    rv[j][2 * k + 1] = ring[b * RP + lane + j * RP];
+                for (int i = 0; i < HB; ++i) {
+                    rv[i][2 * k] = ring[(ta[k] + h * HB + i) * RP + lane];
+                    rv[i][2 * k + 1] = ring[(tb[k] + h * HB + i) * RP + lane];
                 }
             }
-            const int it0 = g * G;
-            auto emit = [&](int j, int voff) {
-                if constexpr (kInt) {
-                    double U = 0.0;
 #pragma unroll
-                    for (int k = 0; k < KT; ++k)
-                        U = fma(double(wm[k]), double(uint32_t(rv[j][2 * k] - rv[j][2 * k + 1])), U);
-                    __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div_f64(U, ip.G2d, ip.G2halfd, ip.invG2d)),
-                                                         rs_dst, voff, 0, 0);
+            for (int i = 0; i < HB; ++i) {
+                const int k = kb + h * HB + i;
+                const bool live = k >= 0 && k < tg.hs;
+                uint32_t vo;
+                if (ostep == 1) {
+                    vo = live ? ocol + uint32_t(k) * dstr : uint32_t(kDropOffset);
                 } else {
-                    float o = c2dc;
-#pragma unroll
-                    for (int k = 0; k < KT; ++k) o = fmaf(wf[k], rv[j][2 * k] - rv[j][2 * k + 1], o);
-                    store_out<Tr>(rs_dst, voff, 0, o);
+                    vo = (live && rr == 0) ? ocol + uint32_t(qrow - oq0) * dstr : uint32_t(kDropOffset);
+                    if (++rr == ostep) { rr = 0; ++qrow; }
                 }
-            };
-            if (ostep == 1) {
-                const uint32_t og = (it0 >= tg.emit0) ? ocol + uint32_t(it0 - tg.emit0) * dstr : uint32_t(kDropOffset);
+                if constexpr (kInt) {
+                    uint64_t U = 0;
 #pragma unroll
-                for (int j = 0; j < G; ++j) emit(j, int(og + uint32_t(j) * dstr));
-            } else {
-                // strided output: rows y = 0, ostep, 2 ostep, ... only (a
-                // uniform test per row), stored at output row y / ostep
-                const int yb = tg.y0 + it0 - tg.emit0;      // image row of this group's first output
-                int q = floor_div(yb, ostep);
-                int rr = yb - q * ostep;
+                    for (int k2 = 0; k2 < KT; ++k2)
+                        U += uint64_t(wm[k2]) * uint64_t(rv[i][2 * k2] - rv[i][2 * k2 + 1]);
+                    __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, int(vo), 0, 0);
+                } else {
+                    float o = cdc;
 #pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    if (rr == 0 && it0 + j >= tg.emit0)
-                        emit(j, int(ocol + uint32_t(q - oq0) * dstr));
-                    if (++rr == ostep) { rr = 0; ++q; }
+                    for (int k2 = 0; k2 < KT; ++k2) o = fmaf(wf[k2], rv[i][2 * k2] - rv[i][2 * k2 + 1], o);
+                    store_out<Tr>(rs_dst, int(vo), 0, o);
                 }
             }
-            slot0 += G;
-            slot0 -= (slot0 >= L) ? L : 0;
-          }
         }
+        slot_m += MB;
+        slot_m -= (slot_m >= L) ? L : 0;
     }
 }
 
-// One task: 64 sample-columns x hs output rows of image `ip`.
-template <class Tr, int C, int SEG, int NPL, int KT, bool PC = false>
+// One task: 64 sample-columns x hs output rows of image `ip`, on one wave
+// (CO = false) or on a workgroup of kCoWaves waves (CO = true).
+template <class Tr, int C, int SEG, int NPL, int KT, bool CO = false>
 __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t* lds)
 {
     constexpr int G = kWave / SEG;
@@ -919,7 +991,9 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
     }
     const int strip = task % ip.nstrips;
     const int seg = task / ip.nstrips;
-    const int pre = (G - (2 * ip.R + 1) % G) % G;
+    // the one-wave form starts pre < G rows earlier, so that emission starts
+    // on a group boundary; the cooperative form emits per row
+    const int pre = CO ? 0 : (G - (2 * ip.R + 1) % G) % G;
     tg.s0 = strip * kWave;
     tg.y0 = seg * ip.hs;
     tg.hs = min(ip.hs, ip.H - tg.y0);
@@ -930,9 +1004,9 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
     tg.ybase = tg.y0 - ip.R - 1 - pre;
     const int WC = ip.W * C;
     const bool interior = ip.vec && tg.a0 >= 0 && tg.a0 + SEG * NPL <= WC;
-    if constexpr (PC) {
-        if (interior) stream_task_pc<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
-        else stream_task_pc<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
+    if constexpr (CO) {
+        if (interior) stream_task_co<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
+        else stream_task_co<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
     } else {
         if (interior) stream_task<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
         else stream_task<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
@@ -951,9 +1025,9 @@ __device__ __forceinline__ int xcd_task(int b, int n)
     return x * q + min(x, rem) + i;
 }
 
-// One task per workgroup of two waves (row-pass and column-pass waves).
+// One task per workgroup of kCoWaves waves (the cooperative form).
 template <class Tr, int C, int SEG, int NPL, int KT>
-__global__ __launch_bounds__((kProducers + 1) * kWave) void k_single_pc(ImgParams ip)
+__global__ __launch_bounds__(kCoWaves * kWave) void k_single_co(ImgParams ip)
 {
     extern __shared__ uint32_t lds[];
     run_task<Tr, C, SEG, NPL, KT, true>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
@@ -990,13 +1064,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     }
 }
 
-// Persistent batch kernel, two-wave form: each workgroup pops (image, task)
-// items and runs them as a row-pass / column-pass pair.  LDS word 0 carries
-// the popped index to both waves; the task's LDS starts 16 bytes later.
+// Persistent batch kernel, cooperative form: each workgroup pops (image,
+// task) items and runs them on its kCoWaves waves.  LDS word 0 carries the
+// popped index to every wave; the task's LDS starts 16 bytes later.
 template <class Tr, int C, int KT, int S0, int N0, int S1, int N1, int S2, int N2, int S3, int N3>
-__global__ __launch_bounds__((kProducers + 1) * kWave) void k_batch_pc(const ImgParams* __restrict__ imgs,
-                                                       const BatchTask* __restrict__ tasks, int ntasks,
-                                                       unsigned* __restrict__ counter)
+__global__ __launch_bounds__(kCoWaves * kWave) void k_batch_co(const ImgParams* __restrict__ imgs,
+                                                              const BatchTask* __restrict__ tasks, int ntasks,
+                                                              unsigned* __restrict__ counter)
 {
     extern __shared__ uint32_t lds[];
     uint32_t* tl = lds + kBatchSlotWords;
@@ -1004,14 +1078,14 @@ __global__ __launch_bounds__((kProducers + 1) * kWave) void k_batch_pc(const Img
         if (threadIdx.x == 0) lds[0] = atomicAdd(counter, 1u);
         __syncthreads();
         const unsigned t = __builtin_amdgcn_readfirstlane(lds[0]);
-        if (t >= unsigned(ntasks)) break;                  // the same for both waves
+        if (t >= unsigned(ntasks)) break;                  // the same for every wave
         const BatchTask bt = tasks[t];
         const ImgParams& ip = imgs[bt.img];
         if (ip.seg == S0 && ip.npl == N0) run_task<Tr, C, S0, N0, KT, true>(ip, bt.task, tl);
         else if (ip.seg == S1 && ip.npl == N1) run_task<Tr, C, S1, N1, KT, true>(ip, bt.task, tl);
         else if (ip.seg == S2 && ip.npl == N2) run_task<Tr, C, S2, N2, KT, true>(ip, bt.task, tl);
         else if (ip.seg == S3 && ip.npl == N3) run_task<Tr, C, S3, N3, KT, true>(ip, bt.task, tl);
-        __syncthreads();                                   // both waves are done with the slot and the tiles
+        __syncthreads();                                   // every wave is done with the slot and the tiles
     }
 }
 

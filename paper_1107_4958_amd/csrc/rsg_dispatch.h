@@ -28,11 +28,11 @@ inline int set_lds_limit(const void* fn, uint32_t bytes)
 template <class Tr, int C, int SEG, int NPL, int KT>
 int launch_one(const ImgParams& ip, hipStream_t st)
 {
-    if (ip.pc) {
-        auto fn = dev::k_single_pc<Tr, C, SEG, NPL, KT>;
+    if (ip.co) {
+        auto fn = dev::k_single_co<Tr, C, SEG, NPL, KT>;
         int rc = set_lds_limit(reinterpret_cast<const void*>(fn), ip.lds_bytes);
         if (rc != RSG_OK) return rc;
-        hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3((kProducers + 1) * kWave), ip.lds_bytes, st, ip);
+        hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3(kCoWaves * kWave), ip.lds_bytes, st, ip);
         return RSG_OK;
     }
     auto fn = dev::k_single<Tr, C, SEG, NPL, KT>;
@@ -85,12 +85,12 @@ template <class Tr, int C, int KT>
 int batch_one(const BatchClassLaunch& b, hipStream_t st)
 {
     using Lo = Layouts<C>;
-    if (b.pc) {
-        auto fn = dev::k_batch_pc<Tr, C, KT, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2], Lo::N[2], Lo::S[3],
+    if (b.co) {
+        auto fn = dev::k_batch_co<Tr, C, KT, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2], Lo::N[2], Lo::S[3],
                                   Lo::N[3]>;
         int rc = set_lds_limit(reinterpret_cast<const void*>(fn), b.lds);
         if (rc != RSG_OK) return rc;
-        hipLaunchKernelGGL(fn, dim3(b.grid), dim3((kProducers + 1) * kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks,
+        hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kCoWaves * kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks,
                            b.d_counter);
         return RSG_OK;
     }

@@ -1,5 +1,7 @@
-// Host-side kernel design for the running-sum Gaussian filter (FP64; the only
-// FP64 arithmetic of the library).
+// Host-side kernel design for the running-sum Gaussian filter, in FP64.  FP64
+// is used only on the host: here, and by the planner for two constants
+// derived from these weights (the FP32 reciprocal of G^2 and the DC gain of
+// the FP32 weights); the kernels compute in FP32 and in integers.
 //
 //   Section 4.1  quadratic-form kernel error E2 = (g - ghat)^T A (g - ghat)
 //                (Eq. mahal) with A_st = Phi(s - t), Phi the autocorrelation

@@ -27,10 +27,9 @@ constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies
 #define RSG_PREFETCH 2
 #endif
 constexpr int kPrefetch = RSG_PREFETCH;   // groups of row loads in flight per wave
-#ifndef RSG_PRODUCERS
-#define RSG_PRODUCERS 1
-#endif
-constexpr int kProducers = RSG_PRODUCERS;   // row-pass waves per task of the multi-wave fused form
+constexpr int kCoWaves = 4;        // waves per task of the cooperative fused form
+constexpr int kCoRows = 8;         // rows per wave per step of the cooperative form
+constexpr int kCoStep = kCoWaves * kCoRows;   // rows per step
 constexpr int64_t kOffsetLimit = int64_t(1) << 30;   // every byte offset a task touches stays below this
 
 // Everything one image's kernel needs; plain data, copied to the device for
@@ -51,14 +50,14 @@ struct ImgParams {
     uint64_t G2;                   // G^2 (uint8 rounding denominator)
     uint64_t G2half;               // floor(G^2 / 2)
     float invG2;                   // 1 / G^2 rounded to FP32 (quotient estimate)
-    double G2d, G2halfd, invG2d;   // the same in FP64 (exact: G^2 < 2^48)
     int32_t R;                     // max r
     // tile plan
     int32_t seg;                   // lanes per row in the row scan (16, 32, 64)
     int32_t npl;                   // samples per lane in the row scan
     int32_t G;                     // input rows per group = 64 / seg
     int32_t hs;                    // output rows per task
-    int32_t L;                     // column ring length: roundup(2R + 1 + G, G) (+ G mirror rows)
+    int32_t L;                     // one-wave form: column ring length roundup(2R + 1 + G, G) (+ G mirror rows)
+    int32_t Lco;                   // cooperative form: roundup(kCoStep + 2R + 1, kCoRows) (+ kCoRows mirror rows)
     int32_t align;                 // span start alignment (samples)
     int32_t vec;                   // 1: rows allow vector loads of one chunk
     int32_t nstrips, nsegs, ntasks;
@@ -70,7 +69,7 @@ struct ImgParams {
     int32_t step;                  // output stride in pixels along both axes (1: every pixel; two-pass only)
     int32_t nslices;               // fused path: a stack of this many equal images (<= 1: one image)
     int64_t slice_stride;          // elements from one image of the stack to the next (source and destination)
-    int32_t pc;                    // fused path: 1 = producer / consumer workgroups of two waves
+    int32_t co;                    // fused path: 1 = cooperative workgroups of kCoWaves waves, 0 = one wave
     int32_t pnpl[2];               // samples per lane of pass A, pass B
     int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
     uint32_t plds[2];              // LDS bytes per workgroup of pass A, pass B
@@ -114,13 +113,11 @@ struct PassParams {
     float dc32;
     uint64_t G2, G2half;
     float invG2;
-    double G2d, G2halfd, invG2d;
     int32_t boundary;
     int32_t vec;                   // rows allow 16-byte chunk loads
     int32_t win_pitch;             // LDS words per wave window
     int32_t win_shift;             // window start offset (aligns its new part to 16 bytes)
     int32_t ostep;                 // store every ostep-th pixel of a row (1: all), compacted
-    double inv_ostep;              // 1.0 / ostep
 };
 
 // One unit of work of a batched launch.
@@ -182,7 +179,7 @@ inline uint32_t pass_lds_bytes(int npl, int hw, int stages, int tr = kPassRowsHo
 // One persistent launch over the tasks of one (dtype, C, kt) class.
 struct BatchClassLaunch {
     int dtype, C, kt;
-    int pc;                        // 1: two-wave workgroups (LDS includes the task slot)
+    int co;                        // 1: cooperative workgroups (LDS includes the task slot)
     int grid;
     uint32_t lds;
     const ImgParams* d_imgs;
@@ -211,12 +208,12 @@ inline void scan_layout(int C, int i, int* seg, int* npl)
 // 32 (mod 64) words puts the pair in opposite halves of the 64 banks.  The
 // column ring keeps the dense 64-word pitch (one word per lane).
 constexpr int row_tile_pitch(int seg, int npl) { return seg * npl + 32; }
-// Producer / consumer form: one row tile per row-pass wave, a two-slot
-// queue of kProducers groups of G rows, and the ring of L + G rows.
-inline uint32_t tile_lds_bytes_pc(int seg, int npl, int L)
+// Cooperative form: one row tile per wave, one block total per wave and
+// column, and the ring of Lco + kCoRows rows.
+inline uint32_t tile_lds_bytes_co(int seg, int npl, int Lco)
 {
     const int G = kWave / seg;
-    return uint32_t(4 * (kProducers * G * row_tile_pitch(seg, npl) + 2 * kProducers * G * kWave + (L + G) * kWave));
+    return uint32_t(4 * (kCoWaves * G * row_tile_pitch(seg, npl) + kCoWaves * kWave + (Lco + kCoRows) * kWave));
 }
 // Two row tiles (double-buffered) and the ring of L + G rows.
 inline uint32_t tile_lds_bytes(int seg, int npl, int L)
@@ -228,13 +225,22 @@ inline uint32_t tile_lds_bytes(int seg, int npl, int L)
 // 16 bytes of LDS (which keeps the tiles 16-byte aligned).
 constexpr int kBatchSlotWords = 4;
 
-// h_stage: optional pinned host buffer of >= batch_workspace_bytes() used to
-// stage the work list (must not be reused before the copy has executed);
-// NULL stages through pageable memory.
+// Workspace of a batched launch: a header (class counters, ImgParams, task
+// entries, PassParams), copied from the host at launch, then the
+// intermediates of the batch's two-pass images, carved from the same
+// caller-provided buffer.  ntasks: tasks of the fused images plus row blocks
+// of the two-pass images.
+size_t batch_header_bytes(int nimg, int64_t ntasks);
+size_t batch_mid_bytes(const ImgParams* imgs, int nimg);
+size_t batch_workspace_bytes(const ImgParams* imgs, int nimg, int64_t ntasks);
+// h_stage: optional pinned host buffer of >= batch_header_bytes() used to
+// stage the header (must not be reused before the copy has executed); NULL
+// stages through pageable memory.  Allocates no device memory.
 int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, int ntasks,
                  void* d_ws, size_t ws_bytes, hipStream_t stream, void* h_stage = nullptr);
-// ntasks: tasks of the fused images plus row blocks of the two-pass images.
-size_t batch_workspace_bytes(int nimg, int ntasks);
+// Two-pass path of one image with its intermediate (>= mid_bytes(ip)) given.
+size_t mid_bytes(const ImgParams& ip);
+int launch_two_pass_into(const ImgParams& ip, void* mid, hipStream_t stream);
 
 // Sizes of the element types.
 inline int dtype_size(int dt) { return dt == RSG_U8 ? 1 : (dt == RSG_F32 ? 4 : 2); }

@@ -2,7 +2,8 @@
 // launch, or the two launches of the two-pass path around a stream-ordered
 // intermediate) and batches (one persistent launch per fused class of
 // element type, channel count, tap count and form, then the two-pass images'
-// row blocks grouped per pass instantiation).
+// row blocks grouped per pass instantiation, with every intermediate carved
+// from the caller's workspace).
 #include "rsg_internal.h"
 
 #include <algorithm>
@@ -36,7 +37,6 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
     const int WoC = (ip.W + step - 1) / step * ip.C;   // intermediate rows: kept pixels x channels
     const int npl = ip.pnpl[pass];
     pp.ostep = step;
-    pp.inv_ostep = 1.0 / double(step);
     if (pass == 0) {                       // image rows -> intermediate (W*C) x H
         pp.src = ip.src;
         pp.dst = mid;
@@ -68,9 +68,6 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
     pp.G2 = ip.G2;
     pp.G2half = ip.G2half;
     pp.invG2 = ip.invG2;
-    pp.G2d = ip.G2d;
-    pp.G2halfd = ip.G2halfd;
-    pp.invG2d = ip.invG2d;
     pp.boundary = ip.boundary;
     const int hw = (2 * ip.R + 1) * (pass == 0 ? ip.C : 1);
     pp.win_pitch = pass_win_pitch(npl, hw);
@@ -78,16 +75,33 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
     return pp;
 }
 
-// Both passes on `stream`, through an intermediate allocated in stream order.
+}  // namespace
+
+size_t mid_bytes(const ImgParams& ip)
+{
+    if (ip.path != kPathTwoPass) return 0;
+    const int step = ip.step > 1 ? ip.step : 1;
+    return size_t(ip.H) * size_t((ip.W + step - 1) / step) * size_t(ip.C) * 4;
+}
+
+int launch_two_pass_into(const ImgParams& ip, void* mid, hipStream_t stream)
+{
+    int rc = launch_pass(ip, 0, pass_params(ip, 0, mid), stream);
+    if (rc == RSG_OK) rc = launch_pass(ip, 1, pass_params(ip, 1, mid), stream);
+    return rc;
+}
+
+namespace {
+
+// Both passes on `stream`, through an intermediate allocated in stream order
+// (the single-image entry points take no workspace).
 int launch_two_pass(const ImgParams& ip, hipStream_t stream)
 {
     void* mid = nullptr;
-    const int step = ip.step > 1 ? ip.step : 1;
-    const size_t bytes = size_t(ip.H) * size_t((ip.W + step - 1) / step) * size_t(ip.C) * 4;
+    const size_t bytes = mid_bytes(ip);
     if (hipMallocAsync(&mid, bytes, stream) != hipSuccess)
         return set_error(RSG_ENOMEM, "cannot allocate the %zu-byte intermediate of the two-pass path", bytes);
-    int rc = launch_pass(ip, 0, pass_params(ip, 0, mid), stream);
-    if (rc == RSG_OK) rc = launch_pass(ip, 1, pass_params(ip, 1, mid), stream);
+    int rc = launch_two_pass_into(ip, mid, stream);
     if (hipFreeAsync(mid, stream) != hipSuccess && rc == RSG_OK)
         rc = set_error(RSG_EDEVICE, "cannot release the two-pass intermediate");
     return rc;
@@ -133,13 +147,25 @@ int64_t pass_blocks(const ImgParams* imgs, int nimg)
 }
 
 // Workspace: [counters, one per class][ImgParams x nimg][task entries x ntasks]
-// [PassParams x 2 nimg].  Task entries (8 bytes) are the fused images'
-// BatchTasks followed by the (pass parameters, row block) pairs of the
-// two-pass images.
-size_t batch_workspace_bytes(int nimg, int ntasks)
+// [PassParams x 2 nimg] (the header), then one intermediate per two-pass
+// image.  Task entries (8 bytes) are the fused images' BatchTasks followed by
+// the (pass parameters, row block) pairs of the two-pass images.
+size_t batch_header_bytes(int nimg, int64_t ntasks)
 {
     return up(sizeof(unsigned) * kMaxClasses) + up(sizeof(ImgParams) * size_t(nimg)) +
            up(sizeof(BatchTask) * size_t(ntasks)) + up(sizeof(PassParams) * 2 * size_t(nimg));
+}
+
+size_t batch_mid_bytes(const ImgParams* imgs, int nimg)
+{
+    size_t b = 0;
+    for (int i = 0; i < nimg; ++i) b += up(mid_bytes(imgs[i]));
+    return b;
+}
+
+size_t batch_workspace_bytes(const ImgParams* imgs, int nimg, int64_t ntasks)
+{
+    return batch_header_bytes(nimg, ntasks) + batch_mid_bytes(imgs, nimg);
 }
 
 int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, int ntasks, void* d_ws,
@@ -147,38 +173,33 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
 {
     static_assert(sizeof(BatchTask) == sizeof(int2), "task entries share one region");
     const int64_t nblocks = pass_blocks(h_imgs, nimg);
-    const size_t need = batch_workspace_bytes(nimg, int(ntasks + nblocks));
+    const size_t hdr = batch_header_bytes(nimg, ntasks + nblocks);
+    const size_t need = hdr + batch_mid_bytes(h_imgs, nimg);
     if (ws_bytes < need) return set_error(RSG_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, need);
 
     // fused images: group the tasks by kernel class, keeping their order
     std::map<std::tuple<int, int, int, int>, std::vector<BatchTask>> classes;
     for (int t = 0; t < ntasks; ++t) {
         const ImgParams& ip = h_imgs[h_tasks[t].img];
-        classes[std::make_tuple(ip.dtype, ip.C, ip.kt, ip.pc)].push_back(h_tasks[t]);
+        classes[std::make_tuple(ip.dtype, ip.C, ip.kt, ip.co)].push_back(h_tasks[t]);
     }
 
-    // two-pass images: one intermediate for all, pass parameters 2j (A) and
-    // 2j + 1 (B) for the j-th of them, row blocks grouped by instantiation
+    // two-pass images: intermediates after the header, pass parameters 2j
+    // (A) and 2j + 1 (B) for the j-th of them, row blocks grouped by
+    // instantiation
     std::vector<int> two;
-    size_t mid_bytes = 0;
     for (int i = 0; i < nimg; ++i)
-        if (h_imgs[i].path == kPathTwoPass) {
-            two.push_back(i);
-            mid_bytes += up(size_t(h_imgs[i].H) * size_t(h_imgs[i].W) * size_t(h_imgs[i].C) * 4);
-        }
-    void* mid = nullptr;
-    if (!two.empty() && hipMallocAsync(&mid, mid_bytes, stream) != hipSuccess)
-        return set_error(RSG_ENOMEM, "cannot allocate the %zu-byte intermediate of the two-pass images", mid_bytes);
+        if (h_imgs[i].path == kPathTwoPass) two.push_back(i);
     std::vector<PassParams> pps(2 * two.size());
     using PassKey = std::tuple<int, int, int, int, int, int, int>;   // pass, dtype, C, npl, kt, stages, rows
     std::map<PassKey, std::vector<int2>> pclasses;
     std::map<PassKey, uint32_t> plds;
     {
-        size_t off = 0;
+        size_t off = hdr;
         for (size_t j = 0; j < two.size(); ++j) {
             const ImgParams& ip = h_imgs[two[j]];
-            void* slice = static_cast<char*>(mid) + off;
-            off += up(size_t(ip.H) * size_t(ip.W) * size_t(ip.C) * 4);
+            void* slice = static_cast<char*>(d_ws) + off;
+            off += up(mid_bytes(ip));
             for (int pass = 0; pass < 2; ++pass) {
                 pps[2 * j + pass] = pass_params(ip, pass, slice);
                 const PassKey key(pass, ip.dtype, pass == 0 ? ip.C : 1, ip.pnpl[pass], ip.kt, ip.pst[pass],
@@ -195,10 +216,10 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
     std::vector<char> pageable;
     char* host = static_cast<char*>(h_stage);
     if (!host) {
-        pageable.assign(need, 0);
+        pageable.assign(hdr, 0);
         host = pageable.data();
     } else {
-        std::memset(host, 0, need);
+        std::memset(host, 0, hdr);
     }
     const size_t o_img = up(sizeof(unsigned) * kMaxClasses);
     const size_t o_task = o_img + up(sizeof(ImgParams) * size_t(nimg));
@@ -214,7 +235,7 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         pos += kv.second.size();
     }
     if (!pps.empty()) std::memcpy(host + o_pp, pps.data(), sizeof(PassParams) * pps.size());
-    hipError_t e = hipMemcpyAsync(d_ws, host, need, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(d_ws, host, hdr, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return set_error(RSG_EDEVICE, "workspace copy failed: %s", hipGetErrorString(e));
 
     int dev = 0, ncu = 0;
@@ -229,16 +250,16 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         b.dtype = std::get<0>(kv.first);
         b.C = std::get<1>(kv.first);
         b.kt = std::get<2>(kv.first);
-        b.pc = std::get<3>(kv.first);
+        b.co = std::get<3>(kv.first);
         b.lds = 0;
         for (const BatchTask& t : kv.second) {
             const ImgParams& ip = h_imgs[t.img];
-            b.lds = std::max(b.lds, b.pc ? ip.lds_bytes + 4 * kBatchSlotWords : ip.lds_one);
+            b.lds = std::max(b.lds, b.co ? ip.lds_bytes + 4 * kBatchSlotWords : ip.lds_one);
         }
         // resident workgroups per CU are bounded by LDS (160 KiB per CU on
         // gfx950); extra workgroups only start late and find the list empty
         int per_cu = b.lds ? int((160u * 1024u) / b.lds) : 16;
-        per_cu = std::max(1, std::min(per_cu, b.pc ? 8 : 16));
+        per_cu = std::max(1, std::min(per_cu, b.co ? 8 : 16));
         b.ntasks = int(kv.second.size());
         b.grid = std::max(1, std::min(b.ntasks, ncu * per_cu));
         b.d_imgs = reinterpret_cast<const ImgParams*>(ws + o_img);
@@ -251,7 +272,6 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
     }
     // two-pass images: every pass-A class, then every pass-B class (the map
     // orders the keys by pass first), so each image's pass B follows its A
-    int rc = RSG_OK;
     for (auto& kv : pclasses) {
         PassBatchLaunch b;
         b.pass = std::get<0>(kv.first);
@@ -265,13 +285,11 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         b.d_pps = reinterpret_cast<const PassParams*>(ws + o_pp);
         b.d_tasks = reinterpret_cast<const int2*>(ws + o_task) + pos;
         b.ntasks = int(kv.second.size());
-        rc = launch_pass_batch(b, stream);
-        if (rc != RSG_OK) break;
+        const int rc = launch_pass_batch(b, stream);
+        if (rc != RSG_OK) return rc;
         pos += kv.second.size();
     }
-    if (mid && hipFreeAsync(mid, stream) != hipSuccess && rc == RSG_OK)
-        rc = set_error(RSG_EDEVICE, "cannot release the two-pass intermediate");
-    return rc;
+    return RSG_OK;
 }
 
 int launch_pass_batch(const PassBatchLaunch& b, hipStream_t stream)

@@ -101,7 +101,7 @@ bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs)
 // wave streams), i.e. ceil(tasks / resident) * (hs + 2R + 1).
 int default_hs(int H, int nstrips, int R, uint32_t lds)
 {
-    const int per_cu = std::max(1, std::min(16, int(kLdsLimit / std::max(lds, 1u))));
+    const int per_cu = std::max(1, std::min(8, int(kLdsLimit / std::max(lds, 1u))));
     const int64_t resident = int64_t(256) * per_cu;
     int best = 32;
     int64_t best_cost = -1;
@@ -109,7 +109,7 @@ int default_hs(int H, int nstrips, int R, uint32_t lds)
         const int h = std::min(hs, H);
         const int64_t tasks = int64_t(nstrips) * ((H + h - 1) / h);
         const int64_t rounds = (tasks + resident - 1) / resident;
-        const int64_t cost = rounds * (h + 2 * R + 1);
+        const int64_t cost = rounds * ((h + 2 * R + 1 + kCoStep - 1) / kCoStep * kCoStep);
         if (best_cost < 0 || cost <= best_cost) { best_cost = cost; best = h; }
         if (hs >= H) break;
     }
@@ -203,9 +203,6 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         p.G2 = b.G * b.G;
         p.G2half = p.G2 / 2;
         p.invG2 = float(1.0 / double(p.G2));
-        p.G2d = double(p.G2);
-        p.G2halfd = double(p.G2half);
-        p.invG2d = 1.0 / p.G2d;
     }
 
     // taps: K < 3 is padded with zero-weight boxes of half-width 0
@@ -282,15 +279,14 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     }
     p.G = kWave / seg;
     p.L = (2 * R + 1 + p.G + p.G - 1) / p.G * p.G;
-    // single launches run each task on two waves (row pass / column pass);
-    // path override 3 keeps the one-wave form (the one the batch kernel uses)
-    // (batched and served images always run the one-wave form, so a plan is
-    // only valid when that form fits too)
-    p.pc = (ov == 3) ? 0 : 1;
+    p.Lco = (kCoStep + 2 * R + 1 + kCoRows - 1) / kCoRows * kCoRows;
+    // single launches, batches and served images run the cooperative form
+    // (kCoWaves waves per task); path override 3 selects the one-wave form
+    p.co = (ov == 3) ? 0 : 1;
     p.lds_one = tile_lds_bytes(seg, npl, p.L);
-    p.lds_bytes = p.pc ? tile_lds_bytes_pc(seg, npl, p.L) : p.lds_one;
-    {   // the batch kernel of the multi-wave form adds its task slot
-        const uint32_t need = std::max(p.lds_bytes + (p.pc ? 4u * kBatchSlotWords : 0u), p.lds_one);
+    p.lds_bytes = p.co ? tile_lds_bytes_co(seg, npl, p.Lco) : p.lds_one;
+    {   // the batch kernel of the cooperative form adds its task slot
+        const uint32_t need = std::max(p.lds_bytes + (p.co ? 4u * kBatchSlotWords : 0u), p.lds_one);
         if (need > kLdsLimit)
             return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", need, kLdsLimit);
     }
@@ -303,9 +299,10 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         // iteration count, times the larger stride) must stay below 2^30
         const int64_t stride_b = std::max(ss, ds) * es;
         auto fits = [&](int h) {
-            // (the multi-wave form pads to whole steps of kProducers groups
-            // and prefetches kPrefetch steps ahead)
-            const int64_t rows = int64_t(h) + 2 * R + 1 + (p.G - 1) + int64_t(kProducers) * (2 * kPrefetch + 1) * p.G;
+            // (the cooperative form pads to whole steps of kCoStep rows and
+            // prefetches into the next step; the one-wave form starts up to
+            // G - 1 rows early and prefetches kPrefetch groups ahead)
+            const int64_t rows = int64_t(h) + 2 * R + 1 + std::max(2 * kCoStep, (p.G - 1) + (2 * kPrefetch + 1) * p.G);
             return rows * stride_b + WC * es <= kOffsetLimit;
         };
         while (hs > 1 && !fits(hs)) hs = (hs + 1) / 2;

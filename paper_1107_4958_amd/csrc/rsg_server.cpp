@@ -3,8 +3,11 @@
 // A scheduler thread owns the device side.  Requests queue in arrival order;
 // whenever an in-flight slot is free it admits the longest prefix of the
 // queue that fits the HBM budget (the image bytes of everything in flight)
-// and the slot's workspace, and filters that group in one persistent batch
-// launch on the slot's stream.  Launches on different streams overlap on the
+// and the slot's workspace (its share of the caller's arena, which holds the
+// work list and the intermediates of two-pass images), and filters that
+// group with one batched launch sequence on the slot's stream.  Planning and
+// launching run outside the server lock, so submit and poll never wait
+// behind a launch.  Launches on different streams overlap on the
 // device, so requests that arrive while earlier ones run start as soon as a
 // slot frees instead of waiting for the whole device to drain.  Completion is
 // detected with one event per launch.  A request filters to the same bits
@@ -47,13 +50,16 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    void* d_ws = nullptr;             // carved from the arena
+    void* d_ws = nullptr;             // carved from the arena: work list and two-pass intermediates
     size_t ws_bytes = 0;
-    void* h_stage = nullptr;          // pinned staging for the work list
-    bool busy = false;
+    void* h_stage = nullptr;          // pinned staging for the work list header, grown on demand
+    size_t stage_bytes = 0;
+    bool busy = false;                // launched (or being launched) and not yet seen complete
     std::vector<uint64_t> tickets;
     size_t footprint = 0;
 };
+
+constexpr size_t kStageInit = 256 << 10;   // initial pinned staging per slot
 
 }  // namespace
 }  // namespace rsg
@@ -77,8 +83,10 @@ struct rsg_server {
 namespace rsg {
 namespace {
 
-// Launch one admitted group on a free slot (called with the lock held).
-void launch_group(rsg_server* s, Slot& slot, std::vector<Request>& group)
+// Plan and launch one admitted group on its slot, without the server lock
+// (only the scheduler thread touches a busy slot).  Returns the status and
+// the launch time.
+int launch_group(Slot& slot, std::vector<Request>& group, uint64_t* t_launch)
 {
     std::vector<rsg_image_desc> descs;
     for (auto& r : group) {
@@ -88,35 +96,32 @@ void launch_group(rsg_server* s, Slot& slot, std::vector<Request>& group)
     std::vector<ImgParams> imgs;
     std::vector<BatchTask> tasks;
     int rc = plan_batch(descs.data(), int(descs.size()), imgs, tasks);
-    const uint64_t t = now_ns();
     if (rc == RSG_OK) {
-        rc = launch_batch(imgs.data(), int(imgs.size()), tasks.data(), int(tasks.size()), slot.d_ws,
-                          slot.ws_bytes, slot.stream, slot.h_stage);
-    }
-    if (rc == RSG_OK && hipEventRecord(slot.done, slot.stream) != hipSuccess) rc = RSG_EDEVICE;
-    slot.tickets.clear();
-    slot.footprint = 0;
-    for (auto& r : group) {
-        r.st.t_start_ns = t;
-        if (rc != RSG_OK) {
-            r.st.done = 1;
-            r.st.status = rc;
-            r.st.t_done_ns = t;
-            s->state[r.ticket] = r.st;
-            s->inflight_bytes -= r.footprint;
-            continue;
+        // the slot's previous launch has completed, so its staging is free
+        const size_t hdr = batch_header_bytes(int(imgs.size()), int64_t(tasks.size()) + pass_blocks(imgs.data(), int(imgs.size())));
+        if (hdr > slot.stage_bytes) {
+            if (slot.h_stage) (void)hipHostFree(slot.h_stage);
+            slot.h_stage = nullptr;
+            slot.stage_bytes = 0;
+            if (hipHostMalloc(&slot.h_stage, hdr, hipHostMallocDefault) != hipSuccess)
+                rc = set_error(RSG_ENOMEM, "cannot pin %zu bytes of staging", hdr);
+            else
+                slot.stage_bytes = hdr;
         }
-        slot.tickets.push_back(r.ticket);
-        slot.footprint += r.footprint;
-        s->state[r.ticket] = r.st;
-        s->running.emplace(r.ticket, r);
     }
-    slot.busy = !slot.tickets.empty();
+    if (rc == RSG_OK)
+        rc = launch_batch(imgs.data(), int(imgs.size()), tasks.data(), int(tasks.size()), slot.d_ws, slot.ws_bytes,
+                          slot.stream, slot.h_stage);
+    // the event is recorded even after a partial launch, so the slot is
+    // reused only once whatever was enqueued has finished
+    if (hipEventRecord(slot.done, slot.stream) != hipSuccess && rc == RSG_OK) rc = RSG_EDEVICE;
+    *t_launch = now_ns();
+    return rc;
 }
 
 void scheduler(rsg_server* s)
 {
-    hipSetDevice(s->device);
+    (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         // completions
@@ -140,19 +145,24 @@ void scheduler(rsg_server* s)
             slot.tickets.clear();
             slot.busy = false;
         }
-        // admission: arrival order, HBM budget, one group per free slot
+        // admission: arrival order, HBM budget, the slot's workspace, one
+        // group per free slot
+        std::vector<std::pair<Slot*, std::vector<Request>>> work;
         for (auto& slot : s->slots) {
             if (s->pending.empty()) break;
             if (slot.busy) continue;
             std::vector<Request> group;
-            size_t bytes = 0;
+            size_t bytes = 0, mid = 0;
             int64_t ntasks = 0;
             while (!s->pending.empty() && int(group.size()) < s->cfg.max_batch) {
                 Request& r = s->pending.front();
                 const size_t fp = r.footprint;
                 if (s->cfg.hbm_budget && s->inflight_bytes + bytes + fp > s->cfg.hbm_budget) break;
-                if (batch_workspace_bytes(int(group.size()) + 1, int(ntasks + r.plan.ntasks)) > slot.ws_bytes) break;
+                const size_t mid_r = batch_mid_bytes(&r.plan, 1);
+                if (batch_header_bytes(int(group.size()) + 1, ntasks + r.plan.ntasks) + mid + mid_r > slot.ws_bytes)
+                    break;
                 bytes += fp;
+                mid += mid_r;
                 ntasks += r.plan.ntasks;
                 r.st.t_admit_ns = now_ns();
                 group.push_back(r);
@@ -160,7 +170,36 @@ void scheduler(rsg_server* s)
             }
             if (group.empty()) break;
             s->inflight_bytes += bytes;
-            launch_group(s, slot, group);
+            slot.busy = true;
+            slot.footprint = bytes;
+            for (auto& r : group) s->state[r.ticket] = r.st;
+            work.emplace_back(&slot, std::move(group));
+        }
+        // plan and launch outside the lock: submit and poll never wait
+        // behind a launch
+        if (!work.empty()) {
+            std::vector<std::pair<int, uint64_t>> res(work.size());
+            lk.unlock();
+            for (size_t i = 0; i < work.size(); ++i) res[i].first = launch_group(*work[i].first, work[i].second, &res[i].second);
+            lk.lock();
+            for (size_t i = 0; i < work.size(); ++i) {
+                Slot& slot = *work[i].first;
+                const int rc = res[i].first;
+                slot.tickets.clear();
+                for (auto& r : work[i].second) {
+                    r.st.t_start_ns = res[i].second;
+                    if (rc != RSG_OK) {               // failed: done now; the slot waits for its event
+                        r.st.done = 1;
+                        r.st.status = rc;
+                        r.st.t_done_ns = res[i].second;
+                        s->state[r.ticket] = r.st;
+                        continue;
+                    }
+                    slot.tickets.push_back(r.ticket);
+                    s->state[r.ticket] = r.st;
+                    s->running.emplace(r.ticket, r);
+                }
+            }
         }
         bool any_busy = false;
         for (auto& slot : s->slots) any_busy |= slot.busy;
@@ -209,8 +248,9 @@ int rsg_server_create(const rsg_server_config* cfg, rsg_server** out)
         sl.stream = s->streams[i % cfg->n_streams];
         sl.d_ws = static_cast<char*>(cfg->d_arena) + per_slot * size_t(i);
         sl.ws_bytes = per_slot;
+        sl.stage_bytes = std::min(per_slot, kStageInit);
         if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc(&sl.h_stage, per_slot, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc(&sl.h_stage, sl.stage_bytes, hipHostMallocDefault) != hipSuccess) {
             for (auto& x : s->slots) {
                 if (x.done) (void)hipEventDestroy(x.done);
                 if (x.h_stage) (void)hipHostFree(x.h_stage);
@@ -246,14 +286,15 @@ int rsg_submit(rsg_server* s, const rsg_image_desc* req, uint64_t* ticket)
     int rc = plan_image(*req, &r.plan);
     if (rc != RSG_OK) return rc;
     const int es = dtype_size(req->dt);
+    // device bytes in flight: the caller's images (a two-pass intermediate
+    // lives in the arena slot, bounded by its size)
     r.footprint = size_t(int64_t(req->H) * r.plan.src_stride * es) + size_t(int64_t(req->H) * r.plan.dst_stride * es);
-    if (r.plan.path == kPathTwoPass)        // its intermediate, allocated in stream order at launch
-        r.footprint += size_t(req->H) * size_t(req->W) * size_t(req->C) * 4;
     const size_t per_slot = s->slots.empty() ? 0 : s->slots[0].ws_bytes;
     if (s->cfg.hbm_budget && r.footprint > s->cfg.hbm_budget)
         return set_error(RSG_ENOMEM, "request needs %zu bytes, budget is %zu", r.footprint, s->cfg.hbm_budget);
-    if (batch_workspace_bytes(1, r.plan.ntasks) > per_slot)
-        return set_error(RSG_ENOMEM, "request work list exceeds the arena slot (%zu bytes)", per_slot);
+    if (batch_workspace_bytes(&r.plan, 1, r.plan.ntasks) > per_slot)
+        return set_error(RSG_ENOMEM, "request workspace (work list and intermediate) exceeds the arena slot (%zu bytes)",
+                         per_slot);
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return set_error(RSG_EINVAL, "server is shutting down");
     if (int(s->pending.size()) >= s->cfg.queue_depth) return set_error(RSG_EBUSY, "queue full");

@@ -30,7 +30,10 @@
 // exact modulo 2^32).  Float inputs subtract a per-row reference (the row's
 // first sample of each channel) before summing, restored through the DC gain
 // of the boxes, and rebase the window to its first entry at every chunk, so
-// no running sum spans more than CW + (2R + 1) C samples.
+// no running sum spans more than CW + (2R + 1) C samples.  Under zero
+// extension the reference is 0: outside samples would otherwise enter as
+// minus the reference, and a box lying mostly outside the row would be a
+// small difference of large sums.
 #pragma once
 
 #include "rsg_device.h"
@@ -120,8 +123,10 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
     if constexpr (!kInt) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
+            // zero extension keeps no reference: outside samples must stay 0,
+            // or boxes reaching far outside would cancel against it
             const int q = pass_clamp<C>(c, len, RSG_REPLICATE);
-            off[c] = Tr_load_one<TrIn>(rs, q * es);
+            off[c] = (boundary == RSG_ZERO) ? 0.0f : Tr_load_one<TrIn>(rs, q * es);
         }
 #pragma unroll
         for (int t = 0; t < NPL; ++t) {
@@ -225,11 +230,10 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
                 for (int kk = 0; kk < KT; ++kk) s += __umul24(wm[kk], win[o + tp[kk]] - win[o + tm[kk]]);
                 word = s;
             } else if constexpr (OUT == kOutU8) {
-                double U = 0.0;                       // exact: see the fused kernel
+                uint64_t U = 0;                       // exact: see the fused kernel
 #pragma unroll
-                for (int kk = 0; kk < KT; ++kk)
-                    U = fma(double(wm[kk]), double(uint32_t(win[o + tp[kk]] - win[o + tm[kk]])), U);
-                word = exact_round_div_f64(U, p.G2d, p.G2halfd, p.invG2d);
+                for (int kk = 0; kk < KT; ++kk) U += uint64_t(wm[kk]) * uint64_t(win[o + tp[kk]] - win[o + tm[kk]]);
+                word = exact_round_div_u(U, p.G2, p.G2half, p.invG2);
             } else {
                 float s = offo[t] * dc;
 #pragma unroll
@@ -276,14 +280,9 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
             if (x >= 0 && x < len && row0 + w < p.rows) {
                 int xo = x;
                 if (ostep > 1) {
-                    // px = q ostep + rem: an FP64 reciprocal estimate (off by
-                    // at most one for px < 2^31) and one correction
                     const int px = x / C;
-                    int q = int(double(px) * p.inv_ostep);
-                    int rem = px - q * ostep;
-                    if (rem < 0) { --q; rem += ostep; }
-                    else if (rem >= ostep) { ++q; rem -= ostep; }
-                    if (rem) continue;
+                    const int q = px / ostep;
+                    if (px - q * ostep) continue;
                     xo = q * C + (x - px * C);
                 }
                 store_pass_out<OUT>(p.dst, int64_t(xo) * p.dst_stride + row0 + w, stg[o * SP + w]);

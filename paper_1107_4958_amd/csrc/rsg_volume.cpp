@@ -72,9 +72,9 @@ extern "C" int rsg_gauss_filter_3d(const void* d_src, void* d_dst, int D, int H,
     } else if (rc == RSG_OK) {                 // two-pass slices: the batched path
         rc = plan_batch(descs.data(), D, imgs, tasks, hs_pref);
         if (rc == RSG_OK) {
-            ws_bytes = batch_workspace_bytes(D, int(int64_t(tasks.size()) + pass_blocks(imgs.data(), D)));
+            ws_bytes = batch_workspace_bytes(imgs.data(), D, int64_t(tasks.size()) + pass_blocks(imgs.data(), D));
             if (hipMallocAsync(&ws, ws_bytes, st) != hipSuccess)
-                rc = set_error(RSG_ENOMEM, "cannot allocate the %zu-byte slice work list", ws_bytes);
+                rc = set_error(RSG_ENOMEM, "cannot allocate the %zu-byte slice workspace", ws_bytes);
         }
         if (rc == RSG_OK)
             rc = launch_batch(imgs.data(), D, tasks.data(), int(tasks.size()), ws, ws_bytes, st, nullptr);
@@ -118,7 +118,7 @@ extern "C" int rsg_gauss_filter_3d(const void* d_src, void* d_dst, int D, int H,
         }
     }
     if (ws && hipFreeAsync(ws, st) != hipSuccess && rc == RSG_OK)
-        rc = set_error(RSG_EDEVICE, "cannot release the slice work list");
+        rc = set_error(RSG_EDEVICE, "cannot release the slice workspace");
     if (hipFreeAsync(mid, st) != hipSuccess && rc == RSG_OK)
         rc = set_error(RSG_EDEVICE, "cannot release the volume intermediate");
     return rc;

@@ -7,7 +7,7 @@
 // segment of hz output slices.  The lane walks positions t = z0 - R - 1 ..
 // z0 + hz - 1 + R, keeps the running sum P of (f - c) (c: the column's first
 // loaded value, restored through the boxes' DC gain, so sums stay at the size
-// of local variations) in an LDS ring of 2R + 2 entries, and emits slice
+// of local variations; 0 under zero extension) in an LDS ring of 2R + 2 entries, and emits slice
 // z = t - R once the ring holds S(z + R) back to S(z - R - 1).  Loads of
 // slice positions are prefetched PFZ steps ahead in registers; consecutive
 // lanes read consecutive addresses.
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_zpass(ZParams p)
     float buf[PFZ];
 #pragma unroll
     for (int j = 0; j < PFZ; ++j) buf[j] = load(1 + j);
-    const float c = buf[0];
+    const float c = (p.boundary == RSG_ZERO) ? 0.0f : buf[0];    // zero extension: outside slices stay 0
     const float cdc = c * dc;
 
     float P = 0.0f;

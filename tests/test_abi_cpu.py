@@ -21,7 +21,7 @@ def _rsg():
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "rsg.h")).read()
     declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(rsg_\w+)\s*\(", header, re.M))
-    assert len(declared) == 16
+    assert len(declared) >= 16
     rsg = _rsg()
     lib = ctypes.CDLL(rsg.LIB_PATH)
     for name in declared:

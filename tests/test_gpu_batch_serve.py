@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synthimg
-from gpu_util import decode, from_device, to_device
+from gpu_util import decode, from_device, rel_max_err, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,7 @@ def _spot_check(img, out, dtype, sigma, K, boundary=0, n=200, seed=0):
     else:
         ref = oracle.box_filter_points(decode(im3, dtype), b["r"], b["w32"].astype(np.float64), ys, xs, cs,
                                        boundary=boundary)
-        den = max(float(np.max(np.abs(im3))), 1e-30)
-        assert float(np.max(np.abs(o3[ys, xs, cs].astype(np.float64) - ref))) / den <= FP32_TOL
+        assert rel_max_err(o3[ys, xs, cs], ref) <= FP32_TOL
 
 
 def _mixed_images():
@@ -200,9 +199,11 @@ def test_serve_budget_and_queue_limits():
     rsg = _rsg()
     big = torch.rand(8192, 8192, device="cuda") * 255       # 256 MiB in, 256 MiB out: ~1 ms at sigma 32
     outs = [torch.empty_like(big) for _ in range(12)]
-    arena = torch.empty(8 << 20, dtype=torch.uint8, device="cuda")
+    # the slot holds the work list and, when the image is planned on the
+    # two-pass path, its 256 MiB intermediate
+    arena = torch.empty(264 << 20, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    one = 3 * big.numel() * 4       # src + dst (+ the intermediate if it is planned on the two-pass path)
+    one = 2 * big.numel() * 4       # src + dst: exactly one request in flight; the 8192 x 8193 one exceeds it
     srv = _server(arena, hbm_budget=one, queue_depth=2, max_inflight=1, n_streams=1, max_batch=1)
     try:
         huge = torch.empty(8192, 8193, device="cuda")
@@ -324,3 +325,52 @@ def test_caller_boxes_in_batch_and_server():
         ys, xs, cs = rng.integers(0, H, 100), rng.integers(0, W, 100), rng.integers(0, C, 100)
         ref = oracle.box_filter_u8_points(im3, o["r"], o["m"], o["G"], ys, xs, cs)
         assert np.array_equal(a3[ys, xs, cs], ref)
+
+
+def test_serve_continuous_batching_overlaps():
+    """Continuous batching: requests submitted while earlier launches are on
+    the device are admitted on other slots and run concurrently with them
+    (their [t_start, t_done] intervals intersect), and every result is the
+    same as the image filtered alone and matches the oracle on samples."""
+    import torch
+    import oracle
+    rsg = _rsg()
+    imgs = [synthimg.image(8192, 8192, 1, "f32", 60 + i) for i in range(2)]
+    srcs = [to_device(im, "f32") for im in imgs]
+    outs = [torch.zeros_like(srcs[i % 2]) for i in range(16)]
+    arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    srv = _server(arena, max_inflight=4, n_streams=4, max_batch=4)
+    try:
+        first = [rsg.rsg_submit(srv, rsg.make_desc(srcs[i % 2], outs[i], 8.0, 3)) for i in range(8)]
+        t_end = time.monotonic() + 30.0
+        while True:                               # the first wave is on the device
+            st = rsg.rsg_poll(srv, first[0])
+            assert not st.done, "first launch finished before the second wave was submitted"
+            if st.t_start_ns:
+                break
+            assert time.monotonic() < t_end
+        second = [rsg.rsg_submit(srv, rsg.make_desc(srcs[i % 2], outs[i], 8.0, 3)) for i in range(8, 16)]
+        stats = _wait_all(srv, first + second)
+    finally:
+        rsg.rsg_server_destroy(srv)
+    assert all(v[0] == rsg.RSG_OK for v in stats.values())
+    A = [stats[t] for t in first]
+    B = [stats[t] for t in second]
+    # a second-wave launch started before some first-wave launch was done
+    overlaps = [(a, b) for a in A for b in B if b[3] < a[4] and a[3] < b[4]]
+    assert overlaps, "no second-wave request ran while a first-wave one was in flight"
+    # admitted while the first wave was still in flight, not after it drained
+    assert min(b[2] for b in B) < max(a[4] for a in A)
+    alone = [_alone(s, 8.0, 3) for s in srcs]
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert torch.equal(o, alone[i % 2]), "request %d differs from the image filtered alone" % i
+    b = oracle.boxes(8.0, 3)
+    for i in range(2):
+        rng = np.random.default_rng(70 + i)
+        ys, xs = rng.integers(0, 8192, 300), rng.integers(0, 8192, 300)
+        ref = oracle.box_filter_points(imgs[i][..., None].astype(np.float64), b["r"], b["w32"].astype(np.float64),
+                                       ys, xs)
+        got = outs[i].cpu().numpy()[ys, xs]
+        assert rel_max_err(got, ref) <= FP32_TOL
