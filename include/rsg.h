@@ -125,7 +125,8 @@ int rsg_fit_boxes_ex(double sigma, int K, rsg_fit_method method, rsg_boxes* out)
  * (and of rsg_box_filter and rsg_gauss_filter_strided): it is taken and
  * released in stream order (hipMallocAsync / hipFreeAsync on `stream`),
  * since the call has no workspace argument; rsg_filter_batch takes it from
- * the caller's workspace instead.  uint8 is computed in exact integers (uint32 running sums,
+ * the caller's workspace and rsg_gauss_filter_noalloc from a fixed scratch
+ * array instead.  uint8 is computed in exact integers (uint32 running sums,
  * a uint64 column combine, one integer rounding at the end: round half up
  * of U / G^2);
  * FP32 / FP16 / BF16 load as FP32 and accumulate in FP32; FP16 / BF16
@@ -137,6 +138,22 @@ int rsg_fit_boxes_ex(double sigma, int K, rsg_fit_method method, rsg_boxes* out)
  * failure). */
 int rsg_gauss_filter(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt,
                      double sigma, int K, rsg_boundary b, void* stream);
+
+/* rsg_gauss_filter for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same plan, kernels and results, but the two-pass path's
+ * intermediate lives in a scratch array of 64 MiB that the library holds on
+ * each device it runs on until the process ends; the call allocates nothing
+ * (no hipMalloc / hipFree / stream-ordered allocation).  The fused path
+ * needs no scratch.  Every call on a device shares that device's array,
+ * whose contents persist between calls (nothing in it needs to start at
+ * zero: the row pass writes every intermediate element before the column
+ * pass reads it); calls that overlap in time on one device race on it.
+ * Errors: as rsg_gauss_filter; RSG_ENOMEM (the image takes the two-pass
+ * path and its intermediate, 4 H W C bytes, exceeds 64 MiB: no launch is
+ * made); RSG_EDEVICE (the array's device address cannot be found). */
+int rsg_gauss_filter_noalloc(const void* d_src, void* d_dst, int H, int W, int C, rsg_dtype dt,
+                             double sigma, int K, rsg_boundary b, void* stream);
 
 /* rsg_gauss_filter with boxes the caller supplies (any fit method, or boxes
  * of its own): K in 1..5, half-widths r_k in [0, 2^26], FP32 weights w32
