@@ -8,10 +8,13 @@ pairs (> 512 MB) that no step finds its image in the 256 MB last-level cache,
 and are resident in HBM before the timed region starts.
 
 Prints ONE JSON line: metric/value/unit of the headline, the roofline of the
-fused kernel (algorithmic bytes per launch / average launch time from HIP
-events on the launch stream, against 8 TB/s HBM3E; HBM traffic from the
-committed rocprofv3 counter summary when it was taken on the current kernel
-sources), the CPU oracle baseline, the uint8 form of the headline and, unless
+fused kernel (algorithmic bytes per launch / launch time, against 8 TB/s
+HBM3E; the --steps timed launches run as 5 repetitions bracketed by HIP
+events on the launch stream and the median repetition is reported; beside it
+the bandwidth of the library's streaming copy kernel on the same buffer
+rotation, replayed from a captured HIP graph; HBM traffic, and for uint8 the VALU work, from the committed
+rocprofv3 counter summary when it was taken on the current kernel sources),
+the CPU oracle baseline, the uint8 form of the headline and, unless
 --quick: the sigma x K grid at 4096^2 (uint8 and FP32), the plain method at
 512^2 with its accuracy against the sampled Gaussian, the mixed batch (256
 three-channel uint8 images in one launch per kernel class against the same
@@ -42,7 +45,7 @@ ES = {"u8": 1, "f32": 4, "f16": 2, "bf16": 2}
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("rsg_device.h", "rsg_dispatch.h", "rsg_plan.cpp", "rsg_internal.h"):
+    for name in ("rsg_device.h", "rsg_dispatch.h", "rsg_plan.cpp", "rsg_internal.h", "rsg_launch.cpp"):
         with open(os.path.join(ROOT, "paper_1107_4958_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     tune = os.path.join(ROOT, "paper_1107_4958_amd", "tune_gfx950.txt")
@@ -89,19 +92,49 @@ def decode(a, dtype):
     return a.astype(np.float64)
 
 
-def time_image(img, dtype, sigma, K, steps, warmup, min_pool_bytes=640 << 20):
-    """Average launch time (ms) of rsg_gauss_filter on `img` over `steps`
-    launches on rotating buffers, timed with HIP events on the launch stream.
-    Returns (ms, last output tensor)."""
+def _pool(base, min_pool_bytes):
+    import torch
+    pair = 2 * base.numel() * base.element_size()
+    npairs = max(2, int(math.ceil(min_pool_bytes / pair)))
+    srcs = [base] + [base.clone() for _ in range(npairs - 1)]
+    dsts = [torch.empty_like(base) for _ in range(npairs)]
+    return srcs, dsts
+
+
+def _timed_reps(launch, steps, reps):
+    """Time `steps` launches as `reps` consecutive repetitions (HIP events on
+    the launch stream between them, synchronised before and after); returns
+    the median per-launch time of the repetitions (ms) and every repetition's."""
+    import torch
+    stream = torch.cuda.current_stream()
+    reps = max(1, min(reps, steps))
+    sizes = [steps // reps + (1 if r < steps % reps else 0) for r in range(reps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    i = 0
+    for r in range(reps):
+        for _ in range(sizes[r]):
+            launch(i)
+            i += 1
+        ev[r + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[r].elapsed_time(ev[r + 1]) / sizes[r] for r in range(reps)]
+    return float(np.median(per)), per
+
+
+def time_image(img, dtype, sigma, K, steps, warmup, min_pool_bytes=640 << 20, reps=5, with_reps=False):
+    """Launch time (ms) of rsg_gauss_filter on `img`: `steps` launches on
+    rotating buffers in `reps` repetitions timed with HIP events on the launch
+    stream, the median repetition's per-launch time.  Returns (ms, last output
+    tensor) or, with_reps, (ms, output, per-repetition ms)."""
     import torch
     import paper_1107_4958_amd as rsg
     base = to_dev(img, dtype)
     H, W = img.shape[:2]
     C = img.shape[2] if img.ndim == 3 else 1
-    pair = 2 * base.numel() * base.element_size()
-    npairs = max(2, int(math.ceil(min_pool_bytes / pair)))
-    srcs = [base] + [base.clone() for _ in range(npairs - 1)]
-    dsts = [torch.empty_like(base) for _ in range(npairs)]
+    srcs, dsts = _pool(base, min_pool_bytes)
+    npairs = len(srcs)
     stream = torch.cuda.current_stream()
     code = rsg.tensor_dtype_code(base)
 
@@ -111,23 +144,78 @@ def time_image(img, dtype, sigma, K, steps, warmup, min_pool_bytes=640 << 20):
 
     for i in range(warmup):
         launch(i)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(steps):
-        launch(i)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps, dsts[(steps - 1) % npairs]
+    ms, per = _timed_reps(launch, steps, reps)
+    out = dsts[(steps - 1) % npairs]
+    return (ms, out, per) if with_reps else (ms, out)
 
 
-def roofline(dtype, H, W, C, ms, traffic=None):
+def copy_ceiling(nbytes, steps, min_pool_bytes=640 << 20, reps=5):
+    """GB/s (read + write) of the library's streaming copy kernel over
+    buffers of the workload's size, on the same rotation as the filter.  A
+    copy of one image is shorter than a Python-side launch, so the launches
+    are captured once in a HIP graph and replayed back to back: the device
+    never idles between copies.  Median of `reps` replays of `steps` copies."""
+    import torch
+    import paper_1107_4958_amd as rsg
+    base = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    srcs, dsts = _pool(base, min_pool_bytes)
+    npairs = len(srcs)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for i in range(3):
+            rsg.rsg_stream_copy(srcs[i % npairs].data_ptr(), dsts[i % npairs].data_ptr(), nbytes, side.cuda_stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        st = torch.cuda.current_stream().cuda_stream
+        for i in range(steps):
+            rsg.rsg_stream_copy(srcs[i % npairs].data_ptr(), dsts[i % npairs].data_ptr(), nbytes, st)
+    graph.replay()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1) / steps)
+    del graph
+    return 2.0 * nbytes / (float(np.median(per)) * 1e-3) / 1e9
+
+
+def valu_record(workload_key: str, ms: float, pixels: int):
+    """VALU work of the fused kernel from the committed rocprofv3 counter
+    summary (SQ_INSTS_VALU per launch, taken on the current kernel sources):
+    lane-operations per pixel, and the busy fraction at this run's launch
+    time (wave64 instructions take 4 cycles on a 16-lane SIMD; 1024 SIMDs at
+    2.4 GHz); None without a current record."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(workload_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_sha") != kernel_source_hash() or not rec.get("valu_insts_per_launch"):
+        return None
+    insts = float(rec["valu_insts_per_launch"])
+    return {"insts_per_launch": insts, "lane_ops_per_px": round(insts * 64 / pixels, 2),
+            "busy_frac": round(insts * 4 / (1024 * ms * 1e-3 * 2.4e9), 3),
+            "source": "profiles/traffic.json (rocprofv3 --pmc SQ_INSTS_VALU)"}
+
+
+def roofline(dtype, H, W, C, ms, traffic=None, copy_gbs=None):
     alg = 2.0 * H * W * C * ES[dtype]              # read once + write once
     achieved = alg / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": int(alg)}
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+         "algorithmic_bytes_per_launch": int(alg)}
+    if copy_gbs:
+        r["copy_ceiling"] = round(copy_gbs, 1)
+        r["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    return r
 
 
 def cpu_baseline(img, dtype, sigma, K, min_seconds=10.0, max_passes=200):
@@ -424,7 +512,10 @@ class _ServingRig:
         self.slot_bytes = 4096 * 4096 * 3 * 4
         self.nslots = nslots
         self.out = torch.empty(self.slot_bytes * nslots, dtype=torch.uint8, device="cuda")
-        self.arena = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+        # the server's arena: 8 slots of 1 GiB, each holding a launch's work
+        # list and the intermediates of its two-pass requests (up to 4 H W C
+        # bytes each: 192 MiB for the largest request)
+        self.arena = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
 
     def desc(self, r, i):
@@ -518,7 +609,7 @@ def serving_workload(n=10000, fractions=(0.25, 0.5, 0.8, 0.95)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500, help="timed launches, split into 5 repetitions")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--sigma", type=float, default=8.0)
@@ -531,7 +622,8 @@ def main():
                     help="only one of the other workloads (--steps timed repetitions), for profiling its kernels")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
-                    help="first run 3 plain device copies of MIB MiB (a known-size reference for HBM counters)")
+                    help="first run 3 copies of MIB MiB with the library's streaming copy kernel "
+                         "(a known-size reference for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -545,11 +637,12 @@ def main():
     import paper_1107_4958_amd  # noqa: F401  (fails loudly if the HIP library is missing)
     import synthimg
 
-    if args.copy_ref:
-        a = torch.empty(args.copy_ref << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    if args.copy_ref:           # the library's streaming copy kernel over MIB MiB, three times
+        import paper_1107_4958_amd as rsg
+        a = torch.empty(args.copy_ref << 20, dtype=torch.uint8, device="cuda").fill_(1)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            rsg.rsg_stream_copy(a.data_ptr(), b.data_ptr(), a.numel(), torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         del a, b
 
@@ -567,7 +660,8 @@ def main():
 
     H = W = args.size
     img = synthimg.image(H, W, 1, args.dtype, 2)
-    ms, out = time_image(img, args.dtype, args.sigma, args.K, args.steps, args.warmup)
+    ms, out, ms_reps = time_image(img, args.dtype, args.sigma, args.K, args.steps, args.warmup, with_reps=True)
+    copy_gbs = copy_ceiling(H * W * ES[args.dtype], 100)
     gpx = H * W / (ms * 1e-3) / 1e9
     key = "%s_%dx%d_s%g_K%d" % (args.dtype, H, W, args.sigma, args.K)
     result = {
@@ -586,7 +680,9 @@ def main():
         "config": {"workload": "%dx%d single-channel %s 1/f image, sigma=%g, K=%d constant boxes, replicate "
                                "boundary, one fused kernel launch per step" % (H, W, args.dtype, args.sigma, args.K),
                    "H": H, "W": W, "C": 1, "sigma": args.sigma, "K": args.K},
-        "roofline": roofline(args.dtype, H, W, 1, ms, traffic_record(key)),
+        "roofline": roofline(args.dtype, H, W, 1, ms, traffic_record(key), copy_gbs),
+        "timing": {"reps": len(ms_reps), "launches_per_rep": args.steps // max(1, len(ms_reps)),
+                   "ms_per_launch_reps": [round(x, 5) for x in ms_reps], "statistic": "median of repetitions"},
         "parity_spot_check": sampled_parity(img, out, args.dtype, args.sigma, args.K),
         # the paper states no run times, throughputs or hardware: only the
         # per-pixel operation count (Table 1) and a speed ranking whose figure
@@ -600,10 +696,12 @@ def main():
         img8 = synthimg.image(H, W, 1, "u8", 2)
         imgs["u8"] = img8
         ms8, out8 = time_image(img8, "u8", args.sigma, args.K, args.steps, args.warmup)
+        key8 = "u8_%dx%d_s%g_K%d" % (H, W, args.sigma, args.K)
         result["u8_variant"] = {"value": round(H * W / (ms8 * 1e-3) / 1e9, 2), "unit": "Gpixel/s",
                                 "ms_per_step": round(ms8, 5),
-                                "roofline": roofline("u8", H, W, 1, ms8,
-                                                     traffic_record("u8_%dx%d_s%g_K%d" % (H, W, args.sigma, args.K))),
+                                "roofline": roofline("u8", H, W, 1, ms8, traffic_record(key8),
+                                                     copy_ceiling(H * W, 100)),
+                                "valu": valu_record(key8, ms8, H * W),
                                 "parity_spot_check": sampled_parity(img8, out8, "u8", args.sigma, args.K)}
     if not args.quick:
         print("bench: sigma x K grid", file=sys.stderr, flush=True)

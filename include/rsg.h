@@ -329,6 +329,17 @@ int rsg_tune_override(int32_t seg_height);
  * RSG_EUNSUPPORTED when the forced path cannot hold the boxes. */
 int rsg_tune_path(int32_t path);
 
+/* ---------------------------------------------------------------------- */
+/* Measurement.                                                            */
+/* ---------------------------------------------------------------------- */
+/* Copy `bytes` from d_src to d_dst on `stream` with a plain streaming copy
+ * kernel (16-byte loads and stores, eight per thread in flight): the
+ * achievable bandwidth the benchmark reports beside the filter's roofline.
+ * Both buffers 16-byte aligned and not overlapping.
+ * Errors: RSG_EINVAL (NULL or misaligned pointers), RSG_EUNSUPPORTED (more
+ * than 2^31 blocks), RSG_EDEVICE (launch failure). */
+int rsg_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
+
 /* Message for the last failure on the calling thread ("" if none). */
 const char* rsg_last_error(void);
 

@@ -11,7 +11,7 @@ Entry points carry the C names (``rsg_fit_boxes``, ``rsg_fit_boxes_ex``,
 ``rsg_gauss_filter_3d``, ``rsg_filter_batch_workspace``, ``rsg_filter_batch``,
 ``rsg_server_create``, ``rsg_submit``, ``rsg_poll``, ``rsg_server_destroy``,
 ``rsg_plan_shape``, ``rsg_tune_override``, ``rsg_tune_path``,
-``rsg_last_error``); ``filter_tensor``, ``filter_strided_tensor``,
+``rsg_stream_copy``, ``rsg_last_error``); ``filter_tensor``, ``filter_strided_tensor``,
 ``filter_volume_tensor`` and ``filter_batch_tensors`` wrap them for torch
 tensors.
 
@@ -111,7 +111,7 @@ class rsg_req_stats(ctypes.Structure):
 SYMBOLS = ("rsg_fit_boxes", "rsg_gauss_filter", "rsg_filter_batch_workspace", "rsg_filter_batch",
            "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_plan_shape",
            "rsg_tune_override", "rsg_tune_path", "rsg_fit_boxes_ex", "rsg_box_filter", "rsg_gauss_filter_strided",
-           "rsg_gauss_filter_3d", "rsg_gauss_filter_noalloc", "rsg_last_error")
+           "rsg_gauss_filter_3d", "rsg_gauss_filter_noalloc", "rsg_stream_copy", "rsg_last_error")
 
 
 def _load():
@@ -133,6 +133,7 @@ def _load():
     lib.rsg_fit_boxes.argtypes = [D, I, ctypes.POINTER(rsg_boxes)]
     lib.rsg_gauss_filter.argtypes = [V, V, I, I, I, I, D, I, I, V]
     lib.rsg_gauss_filter_noalloc.argtypes = [V, V, I, I, I, I, D, I, I, V]
+    lib.rsg_stream_copy.argtypes = [V, V, S, V]
     lib.rsg_fit_boxes_ex.argtypes = [D, I, I, ctypes.POINTER(rsg_boxes)]
     lib.rsg_box_filter.argtypes = [V, V, I, I, I, I, ctypes.POINTER(rsg_boxes), I, V]
     lib.rsg_gauss_filter_strided.argtypes = [V, V, I, I, I, I, D, I, ctypes.POINTER(rsg_boxes), I, I, V]
@@ -196,6 +197,10 @@ def rsg_gauss_filter_noalloc(d_src: int, d_dst: int, H: int, W: int, C: int, dt:
                              boundary: int = RSG_REPLICATE, stream: int = 0) -> None:
     _check(_lib.rsg_gauss_filter_noalloc(ctypes.c_void_p(d_src), ctypes.c_void_p(d_dst), H, W, C, dt,
                                          float(sigma), K, boundary, ctypes.c_void_p(stream)))
+
+
+def rsg_stream_copy(d_src: int, d_dst: int, nbytes: int, stream: int = 0) -> None:
+    _check(_lib.rsg_stream_copy(ctypes.c_void_p(d_src), ctypes.c_void_p(d_dst), int(nbytes), ctypes.c_void_p(stream)))
 
 
 def rsg_box_filter(d_src: int, d_dst: int, H: int, W: int, C: int, dt: int, boxes: rsg_boxes,

@@ -40,3 +40,25 @@ def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.traffic_record("f32_4096x4096_s8_K3") is None
     assert bench.traffic_record("u8_4096x4096_s8_K3") is None
+
+
+def test_valu_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    """uint8 VALU work comes from the committed counter record of the same
+    kernel sources: lane-ops per pixel = instructions x 64 / pixels, busy =
+    instructions x 4 cycles / (1024 SIMDs x time x 2.4 GHz)."""
+    rec = {"u8_4096x4096_s8_K3": {"kernel_sha": "a" * 16, "valu_insts_per_launch": 1.0e7}}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "a" * 16)
+    v = bench.valu_record("u8_4096x4096_s8_K3", 0.05, 4096 * 4096)
+    assert v["lane_ops_per_px"] == pytest.approx(1.0e7 * 64 / 4096 ** 2, abs=0.01)
+    assert v["busy_frac"] == pytest.approx(1.0e7 * 4 / (1024 * 0.05e-3 * 2.4e9), abs=1e-3)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "b" * 16)
+    assert bench.valu_record("u8_4096x4096_s8_K3", 0.05, 4096 * 4096) is None
+
+
+def test_roofline_reports_the_copy_ceiling():
+    rf = bench.roofline("f32", 4096, 4096, 1, 0.05, copy_gbs=5000.0)
+    assert rf["copy_ceiling"] == 5000.0
+    assert rf["frac_of_copy"] == pytest.approx(rf["achieved"] / 5000.0, abs=1e-4)

@@ -77,3 +77,17 @@ def test_pitched_window(dt, H, W, C, x0, pad0, x1, pad1, sigma, K, boundary):
     else:
         ref = oracle.box_filter(decode(img, dt), b["r"], b["w32"].astype(np.float64), boundary)
         assert half_ulp_diff(out, ref, dt) <= 1
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 7, (1 << 20) + 5, 33 << 20])
+def test_stream_copy(nbytes):
+    """The bandwidth reference of the benchmark copies exactly, tail bytes
+    included, and leaves the bytes after the range alone."""
+    import torch
+    import paper_1107_4958_amd as rsg
+    src = torch.randint(0, 256, (nbytes + 64,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    rsg.rsg_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src[:nbytes])
+    assert int(dst[nbytes:].sum()) == 0
