@@ -213,25 +213,25 @@ __device__ __forceinline__ void load_chunk_elem(Chunk<Tr, NPL>& ch, __amdgpu_buf
 }
 
 // uint8 output: round half up of U / G^2, exactly, in integer arithmetic.
-// N = U + floor(G^2 / 2) < 256 G^2 <= 2^56.  The FP32 estimate of N / G^2
-// (N's high word is exact in FP32; three roundings of 2^-24 each keep it
-// within 2^-13 of the quotient, which is below 256), lowered by a margin of
-// 2^-11, truncates to q or q - 1; one 64-bit remainder in [0, 2 G^2)
-// decides.  G^2 < 2^48, so q G^2 needs one 32 x 32 -> 64 product and one
-// 24-bit product for its high word.
-__device__ __forceinline__ uint32_t exact_round_div_u(uint64_t U, uint64_t G2, uint64_t G2half, float invG2)
+// N = U + floor(G^2 / 2) < 256 G^2 <= 2^56.  N >> qsh (qsh per image: the
+// shift that brings 256 G^2 below 2^32) converts to FP32 in one instruction;
+// scaled by invG2s = 2^qsh / G^2 it is within 2^-13 of N / G^2 (the dropped
+// bits are below 2^-23 of G^2 and three roundings of 2^-24 each on a value
+// below 256 stay under 2^-15), so the estimate lowered by a margin of 2^-11
+// truncates to q or q - 1, and one comparison of N with (q + 1) G^2 (a 64-bit
+// multiply-add, G^2 < 2^48) decides.
+__device__ __forceinline__ uint32_t exact_round_div_u(uint64_t U, uint64_t G2, uint64_t G2half, float invG2s, int qsh)
 {
     const uint64_t N = U + G2half;
-    const float nf = fmaf(float(uint32_t(N >> 32)), 4294967296.0f, float(uint32_t(N)));
-    uint32_t q = uint32_t(fmaxf(fmaf(nf, invG2, -0.00048828125f), 0.0f));
-    uint64_t P = uint64_t(q) * uint64_t(uint32_t(G2));
-    P += uint64_t(__umul24(q, uint32_t(G2 >> 32))) << 32;
-    const uint64_t r = N - P;
-    return q + ((r >= G2) ? 1u : 0u);
+    const float nf = float(uint32_t(N >> qsh));
+    const uint32_t q = uint32_t(fmaxf(fmaf(nf, invG2s, -0.00048828125f), 0.0f));
+    uint64_t P1 = uint64_t(q) * uint64_t(uint32_t(G2)) + G2;       // (q + 1) G^2, low word product
+    P1 += uint64_t(__umul24(q, uint32_t(G2 >> 32))) << 32;
+    return q + ((N >= P1) ? 1u : 0u);
 }
 __device__ __forceinline__ uint32_t exact_round_div(uint64_t U, const ImgParams& ip)
 {
-    return exact_round_div_u(U, ip.G2, ip.G2half, ip.invG2);
+    return exact_round_div_u(U, ip.G2, ip.G2half, ip.invG2, ip.qsh);
 }
 
 // One element at byte offset `boff` of a buffer, as float.
@@ -275,6 +275,7 @@ __device__ __forceinline__ void store_out<TrBF16>(__amdgpu_buffer_rsrc_t rs, int
 // Per-task constants.
 struct TaskGeom {
     int s0, y0, hs, a0, off, niter, ybase;
+    int o0;                                    // first output sample of the strip (strided output: kept samples)
     int emit0;                                 // first iteration that emits a row (a multiple of G)
     int64_t slice_off;                         // byte offset of the task's slice (stacked images)
 };
@@ -753,28 +754,33 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
             load_chunk_vec<Tr, NPL>(ch, rs_src, zero_row ? kDropOffset : vec_voff + rowoff, 0);
         }
     };
+    // ---------------- this lane's column ----------------
+    // Output sample oidx of the output row (the image's, or with a strided
+    // output, every ostep-th pixel compacted: the strip then covers 64 kept
+    // samples, so the row taps and the column pass run at kept columns only)
+    // and the input sample s it is centred on.
+    const int ostep = ip.step > 1 ? ip.step : 1;
+    const int orow_len = (ostep > 1) ? (W + ostep - 1) / ostep * C : WC;
+    const int oidx = tg.o0 + lane;
+    const int s = (ostep > 1) ? (oidx / C) * ostep * C + oidx % C : oidx;
+    const bool col_live = oidx < orow_len;
+    const int colL = col_live ? s - tg.a0 : tg.off;      // tile position (lanes past the row: any inside)
     int tp[KT], tm[KT];
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
-        tp[k] = tg.off + lane + ip.r[k] * C;
-        tm[k] = tg.off + lane - (ip.r[k] + 1) * C;
+        tp[k] = colL + ip.r[k] * C;
+        tm[k] = colL - (ip.r[k] + 1) * C;
     }
 
     // ---------------- column setup ----------------
     // Output rows of this task: y0 .. y0 + hs - 1, or with a strided output
-    // (every ostep-th row and pixel, compacted) the kept rows oq0 .. oq1 - 1
-    // of the output image; rows outside the descriptor and dropped columns
-    // are stored to out-of-range offsets.
-    const int ostep = ip.step > 1 ? ip.step : 1;
-    const int s = tg.s0 + lane;
-    int oq0 = tg.y0, nrows = tg.hs, orow_len = WC;
-    uint32_t ocol = (s < WC) ? uint32_t(s * es) : kDropColumn;
+    // the kept rows oq0 .. oq1 - 1 of the output image; rows outside the
+    // descriptor and columns past the row are stored to out-of-range offsets.
+    int oq0 = tg.y0, nrows = tg.hs;
+    const uint32_t ocol = col_live ? uint32_t(oidx * es) : kDropColumn;
     if (ostep > 1) {
         oq0 = (tg.y0 + ostep - 1) / ostep;
         nrows = (tg.y0 + tg.hs - 1) / ostep - oq0 + 1;
-        orow_len = (W + ostep - 1) / ostep * C;
-        const int x = s / C;
-        ocol = (s < WC && x % ostep == 0) ? uint32_t(((x / ostep) * C + (s - x * C)) * es) : kDropColumn;
     }
     const char* dbase = reinterpret_cast<char*>(ip.dst) + tg.slice_off + int64_t(oq0) * dstride;
     const __amdgpu_buffer_rsrc_t rs_dst =
@@ -914,8 +920,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
         }
         __syncthreads();
 
-        // ---- column box differences (Eq. indep) and stores, in two halves
-        //      of the block (fewer taps live at once) ----
+        // ---- column box differences (Eq. indep) and stores ----
         int ta[KT], tb[KT];
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
@@ -924,49 +929,75 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
             ta[k] += (ta[k] < 0) ? L : 0;
             tb[k] += (tb[k] < 0) ? L : 0;
         }
-        // output row of block row i: k = (first iteration of the block) + i - (2R + 1)
+        // output row of block row i: k = (first iteration of the block) + i - (2R + 1);
+        // its byte offset in the output (scalar), or the dropped offset
         const int kb = m * MB + wave * RB - tg.emit0;
-        int qrow = 0, rr = 0;
-        if (ostep > 1) {
-            const int yb = tg.y0 + kb;
-            qrow = floor_div(yb, ostep);
-            rr = yb - qrow * ostep;
-        }
-        constexpr int HB = RB / 2;
+        int soff[RB];
+        if (ostep == 1) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            __builtin_amdgcn_sched_barrier(0);
-            Acc rv[HB][2 * KT];
-#pragma unroll
-            for (int k = 0; k < KT; ++k) {
-#pragma unroll
-                for (int i = 0; i < HB; ++i) {
-                    rv[i][2 * k] = ring[(ta[k] + h * HB + i) * RP + lane];
-                    rv[i][2 * k + 1] = ring[(tb[k] + h * HB + i) * RP + lane];
-                }
+            for (int i = 0; i < RB; ++i) {
+                const int k = kb + i;
+                soff[i] = (k >= 0 && k < tg.hs) ? int(uint32_t(k) * dstr) : kDropOffset;
             }
+        } else {
+            const int yb = tg.y0 + kb;
+            int qrow = floor_div(yb, ostep);
+            int rr = yb - qrow * ostep;
 #pragma unroll
-            for (int i = 0; i < HB; ++i) {
-                const int k = kb + h * HB + i;
-                const bool live = k >= 0 && k < tg.hs;
-                uint32_t vo;
-                if (ostep == 1) {
-                    vo = live ? ocol + uint32_t(k) * dstr : uint32_t(kDropOffset);
-                } else {
-                    vo = (live && rr == 0) ? ocol + uint32_t(qrow - oq0) * dstr : uint32_t(kDropOffset);
-                    if (++rr == ostep) { rr = 0; ++qrow; }
+            for (int i = 0; i < RB; ++i) {
+                const int k = kb + i;
+                soff[i] = (k >= 0 && k < tg.hs && rr == 0) ? int(uint32_t(qrow - oq0) * dstr) : kDropOffset;
+                if (++rr == ostep) { rr = 0; ++qrow; }
+            }
+        }
+        auto combine_store = [&](const Acc (&rv)[2 * KT], int i) {
+            const int vo = int(ocol + uint32_t(soff[i]));
+            if constexpr (kInt) {
+                uint64_t U = 0;
+#pragma unroll
+                for (int k2 = 0; k2 < KT; ++k2) U += uint64_t(wm[k2]) * uint64_t(rv[2 * k2] - rv[2 * k2 + 1]);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, vo, 0, 0);
+            } else {
+                float o = cdc;
+#pragma unroll
+                for (int k2 = 0; k2 < KT; ++k2) o = fmaf(wf[k2], rv[2 * k2] - rv[2 * k2 + 1], o);
+                store_out<Tr>(rs_dst, vo, 0, o);
+            }
+        };
+        if (ostep == 1) {
+            // every row: the taps of half a block at a time (fewer live registers)
+            constexpr int HB = RB / 2;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                __builtin_amdgcn_sched_barrier(0);
+                Acc rv[HB][2 * KT];
+#pragma unroll
+                for (int k = 0; k < KT; ++k) {
+#pragma unroll
+                    for (int i = 0; i < HB; ++i) {
+                        rv[i][2 * k] = ring[(ta[k] + h * HB + i) * RP + lane];
+                        rv[i][2 * k + 1] = ring[(tb[k] + h * HB + i) * RP + lane];
+                    }
                 }
-                if constexpr (kInt) {
-                    uint64_t U = 0;
 #pragma unroll
-                    for (int k2 = 0; k2 < KT; ++k2)
-                        U += uint64_t(wm[k2]) * uint64_t(rv[i][2 * k2] - rv[i][2 * k2 + 1]);
-                    __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, int(vo), 0, 0);
+                for (int i = 0; i < HB; ++i) combine_store(rv[i], h * HB + i);
+            }
+        } else {
+            // strided output: only kept rows read their taps and combine (a
+            // uniform test); a dropped row still issues one store, out of range
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                if (soff[i] != kDropOffset) {
+                    Acc rv[2 * KT];
+#pragma unroll
+                    for (int k = 0; k < KT; ++k) {
+                        rv[2 * k] = ring[(ta[k] + i) * RP + lane];
+                        rv[2 * k + 1] = ring[(tb[k] + i) * RP + lane];
+                    }
+                    combine_store(rv, i);
                 } else {
-                    float o = cdc;
-#pragma unroll
-                    for (int k2 = 0; k2 < KT; ++k2) o = fmaf(wf[k2], rv[i][2 * k2] - rv[i][2 * k2 + 1], o);
-                    store_out<Tr>(rs_dst, int(vo), 0, o);
+                    if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * i, 0, 0);
+                    else store_out<Tr>(rs_dst, kDropOffset - 64 * i, 0, 0.0f);
                 }
             }
         }
@@ -995,6 +1026,10 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
     // on a group boundary; the cooperative form emits per row
     const int pre = CO ? 0 : (G - (2 * ip.R + 1) % G) % G;
     tg.s0 = strip * kWave;
+    tg.o0 = tg.s0;
+    if (CO && ip.step > 1) {                   // a strip of 64 kept output samples: its first input sample
+        tg.s0 = (tg.o0 / C) * ip.step * C + tg.o0 % C;
+    }
     tg.y0 = seg * ip.hs;
     tg.hs = min(ip.hs, ip.H - tg.y0);
     tg.a0 = floor_div(tg.s0 - (ip.R + 1) * C, ip.align) * ip.align;

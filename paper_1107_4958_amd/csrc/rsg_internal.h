@@ -49,7 +49,8 @@ struct ImgParams {
     float dc32;                    // sum_k wf_k (2 r_k + 1): DC gain of the FP32 boxes
     uint64_t G2;                   // G^2 (uint8 rounding denominator)
     uint64_t G2half;               // floor(G^2 / 2)
-    float invG2;                   // 1 / G^2 rounded to FP32 (quotient estimate)
+    float invG2;                   // 2^qsh / G^2 rounded to FP32 (quotient estimate)
+    int32_t qsh;                   // shift that brings 256 G^2 below 2^32
     int32_t R;                     // max r
     // tile plan
     int32_t seg;                   // lanes per row in the row scan (16, 32, 64)
@@ -113,6 +114,7 @@ struct PassParams {
     float dc32;
     uint64_t G2, G2half;
     float invG2;
+    int32_t qsh;
     int32_t boundary;
     int32_t vec;                   // rows allow 16-byte chunk loads
     int32_t win_pitch;             // LDS words per wave window

@@ -68,6 +68,7 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
     pp.G2 = ip.G2;
     pp.G2half = ip.G2half;
     pp.invG2 = ip.invG2;
+    pp.qsh = ip.qsh;
     pp.boundary = ip.boundary;
     const int hw = (2 * ip.R + 1) * (pass == 0 ? ip.C : 1);
     pp.win_pitch = pass_win_pitch(npl, hw);

@@ -202,7 +202,11 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     if (d.dt == RSG_U8) {
         p.G2 = b.G * b.G;
         p.G2half = p.G2 / 2;
-        p.invG2 = float(1.0 / double(p.G2));
+        // the estimate divides N >> qsh (< 2^32) by G^2 / 2^qsh
+        int qsh = 0;
+        while ((p.G2 << 8) > (uint64_t(1) << (32 + qsh))) ++qsh;
+        p.qsh = qsh;
+        p.invG2 = float(std::ldexp(1.0, qsh) / double(p.G2));
     }
 
     // taps: K < 3 is padded with zero-weight boxes of half-width 0
@@ -236,7 +240,15 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     }
 
     // ---- row-scan layout: first (lanes per row, samples per lane) whose
-    //      segment covers the row span [s0 - (R+1)C, s0 + 64 + RC) ----
+    //      segment covers the row span [s0 - (R+1)C, s_63 + RC] of a task's
+    //      64 columns s_0 .. s_63 (consecutive samples; with a strided
+    //      output, the input samples of 64 consecutive kept samples) ----
+    int64_t cols = kWave;
+    if (step > 1) {
+        int64_t np = 0;                              // pixels a strip of 64 kept samples spans
+        for (int k = 0; k < C; ++k) np = std::max<int64_t>(np, ((kWave * k) % C + kWave - 1) / C + 1);
+        cols = ((np - 1) * step + 1) * C;
+    }
     int seg = 0, npl = 0, align = 1;
     for (int i = 0; i < kLayouts && !seg; ++i) {
         int sg, n;
@@ -244,7 +256,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         const int cb = n * es;                       // chunk bytes
         const int unit = gcd_i(cb, 16);              // vector load granule
         const int al = lcm_i(C, std::max(1, unit / es));
-        const int64_t span = int64_t(kWave) + int64_t(2 * R + 1) * C + al - 1;
+        const int64_t span = cols + int64_t(2 * R + 1) * C + al - 1;
         if (span <= int64_t(sg) * n) { seg = sg; npl = n; align = al; }
     }
     if (!seg && !two) {
@@ -290,7 +302,8 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         if (need > kLdsLimit)
             return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", need, kLdsLimit);
     }
-    p.nstrips = int((WC + kWave - 1) / kWave);
+    // a strip is 64 output samples (strided: 64 kept samples)
+    p.nstrips = int((WoC + kWave - 1) / kWave);
 
     // ---- segment height ----
     int hs = hs_pref > 0 ? hs_pref : ((tabled && hs_t > 0) ? hs_t : default_hs(d.H, p.nstrips, R, p.lds_bytes));

@@ -233,7 +233,7 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
                 uint64_t U = 0;                       // exact: see the fused kernel
 #pragma unroll
                 for (int kk = 0; kk < KT; ++kk) U += uint64_t(wm[kk]) * uint64_t(win[o + tp[kk]] - win[o + tm[kk]]);
-                word = exact_round_div_u(U, p.G2, p.G2half, p.invG2);
+                word = exact_round_div_u(U, p.G2, p.G2half, p.invG2, p.qsh);
             } else {
                 float s = offo[t] * dc;
 #pragma unroll
