@@ -299,8 +299,9 @@ int rsg_server_destroy(rsg_server* s);
  * windows) and the LDS is the larger pass's.  Host-only: d->src and d->dst
  * are compared but never dereferenced.  Segment heights come from the tuning
  * table named by the environment variable RSG_TUNE_TABLE (read once, lines
- * "dtype C rlo rhi nlo nhi hs", with R the largest box half-width and n the
- * number of 64-sample strips times H), else from a built-in rule.  This is
+ * "dtype C rlo rhi nlo nhi hs [nc]", with R the largest box half-width, n
+ * the number of 64-sample strips times H and nc the columns per lane of
+ * rsg_tune_columns), else from a built-in rule.  This is
  * the image's own plan; in a batch, uint8 images may get longer segments
  * (same results).  Any output pointer may be NULL.
  * Errors: as rsg_gauss_filter. */
@@ -328,6 +329,19 @@ int rsg_tune_override(int32_t seg_height);
  * Errors: RSG_EINVAL (path not in 0..3); later plans return
  * RSG_EUNSUPPORTED when the forced path cannot hold the boxes. */
 int rsg_tune_path(int32_t path);
+
+/* Process-wide strip width of the fused kernel's workgroups for every later
+ * unstrided plan: 0 lets the planner choose (the tuning table's optional
+ * last field, else one column per lane), 1 gives each lane one sample
+ * column (strips of 64 samples), any larger value the wide form: each lane
+ * owns two adjacent columns at C = 1 (strips of 128 samples) and one
+ * pixel's three channels at C = 3 (strips of 64 pixels); C = 2 and 4 keep
+ * one column per lane.  The wide form shortens the row span each output
+ * pays for and moves a lane's columns with one vector access, at the price
+ * of a larger LDS ring; it falls back to one column where that ring would
+ * not fit.  Results agree to FP32 rounding (bit-identical for uint8).  For
+ * the autotuner and tests.  Errors: RSG_EINVAL (negative). */
+int rsg_tune_columns(int32_t columns);
 
 /* ---------------------------------------------------------------------- */
 /* Measurement.                                                            */

@@ -112,6 +112,14 @@ int rsg_tune_path(int32_t path)
     return RSG_OK;
 }
 
+int rsg_tune_columns(int32_t columns)
+{
+    using namespace rsg;
+    if (columns < 0) return set_error(RSG_EINVAL, "columns per lane must be >= 0");
+    set_nc_override(columns);
+    return RSG_OK;
+}
+
 int rsg_tune_override(int32_t seg_height)
 {
     using namespace rsg;

@@ -50,6 +50,10 @@
 namespace rsg {
 namespace dev {
 
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t v3u __attribute__((ext_vector_type(3)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
 // --------------------------------------------------------------------------
 // DPP (gfx9 row_shr / row_bcast controls)
 // --------------------------------------------------------------------------
@@ -270,6 +274,95 @@ __device__ __forceinline__ void store_out<TrBF16>(__amdgpu_buffer_rsrc_t rs, int
 {
     const uint32_t u = __float_as_uint(v);                          // finite v
     __builtin_amdgcn_raw_buffer_store_b16(uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16), rs, voff, soff, 0);
+}
+
+// NC consecutive output samples of one lane at byte offset vo: one vector
+// store when every sample is inside the row (`full`) and the type allows it
+// (`vec`: 2-byte element types need the destination aligned to the group),
+// else one store per sample, those at or past `nlive` dropped.
+template <class Tr, int NC>
+__device__ __forceinline__ void store_group(__amdgpu_buffer_rsrc_t rs, int vo, const uint32_t (&w)[NC], bool full,
+                                            int nlive, bool vec)
+{
+    constexpr int es = Tr::kSize;
+    if constexpr (NC == 1) {
+        if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, vo, 0, 0);
+        else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0]), rs, vo, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[0]), rs, vo, 0, 0);
+        return;
+    } else {
+        if (full && (es == 4 || vec)) {
+            if constexpr (es == 4) {
+                if constexpr (NC == 2) {
+                    __builtin_amdgcn_raw_buffer_store_b64((v2u){w[0], w[1]}, rs, vo, 0, 0);
+                } else if constexpr (NC == 3) {
+                    __builtin_amdgcn_raw_buffer_store_b96((v3u){w[0], w[1], w[2]}, rs, vo, 0, 0);
+                } else {
+                    __builtin_amdgcn_raw_buffer_store_b128((v4u){w[0], w[1], w[2], w[3]}, rs, vo, 0, 0);
+                }
+            } else if constexpr (es == 2 && NC == 2) {
+                __builtin_amdgcn_raw_buffer_store_b32(w[0] | (w[1] << 16), rs, vo, 0, 0);
+            } else if constexpr (es == 1 && NC == 2) {
+                __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0] | (w[1] << 8)), rs, vo, 0, 0);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, vo + 2 * c, 0, 0);
+                    else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, vo + c, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int o = (c < nlive) ? vo + c * es : kDropOffset;
+                if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[c], rs, o, 0, 0);
+                else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, o, 0, 0);
+                else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, o, 0, 0);
+            }
+        }
+    }
+}
+// The stored bits of an FP32 result in the element type (round to nearest even).
+template <class Tr> __device__ __forceinline__ uint32_t out_bits(float v);
+template <> __device__ __forceinline__ uint32_t out_bits<TrF32>(float v) { return __float_as_uint(v); }
+template <> __device__ __forceinline__ uint32_t out_bits<TrF16>(float v)
+{
+    return __half_as_ushort(__float2half_rn(v));
+}
+template <> __device__ __forceinline__ uint32_t out_bits<TrBF16>(float v)
+{
+    const uint32_t u = __float_as_uint(v);                          // finite v
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// NC consecutive LDS words of one lane (8- or 16-byte aligned for NC = 2, 4).
+template <class Acc, int NC>
+__device__ __forceinline__ void lds_put(Acc* p, const Acc (&v)[NC])
+{
+    if constexpr (NC == 2) {
+        *reinterpret_cast<v2u*>(p) = (v2u){bits(v[0]), bits(v[1])};
+    } else if constexpr (NC == 4) {
+        *reinterpret_cast<v4u*>(p) = (v4u){bits(v[0]), bits(v[1]), bits(v[2]), bits(v[3])};
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) p[c] = v[c];
+    }
+}
+template <class Acc, int NC>
+__device__ __forceinline__ void lds_get(const Acc* p, Acc (&v)[NC])
+{
+    if constexpr (NC == 2) {
+        const v2u t = *reinterpret_cast<const v2u*>(p);
+        v[0] = frombits<Acc>(t[0]);
+        v[1] = frombits<Acc>(t[1]);
+    } else if constexpr (NC == 4) {
+        const v4u t = *reinterpret_cast<const v4u*>(p);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = frombits<Acc>(t[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = p[c];
+    }
 }
 
 // Per-task constants.
@@ -639,7 +732,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 // offsets, so every step issues the same memory operations and the waits
 // for the prefetched loads stay exact.
 // --------------------------------------------------------------------------
-template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE, int NW_ = kCoWaves, int RB_ = kCoRows>
+template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE, int NC = 1, int NW_ = kCoWaves, int RB_ = kCoRows>
 __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
 {
     using Acc = typename Tr::Acc;
@@ -647,7 +740,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     constexpr int G = kWave / SEG;
     constexpr int PW = SEG * NPL;
     constexpr int PP = row_tile_pitch(SEG, NPL);
-    constexpr int RP = kWave;
+    constexpr int RP = kWave * NC;             // words per ring row (the strip's columns)
     constexpr int NW = NW_;                    // waves per task
     constexpr int RB = RB_;                    // rows per wave per step
     constexpr int NGW = RB / G;                // row groups per wave per step
@@ -665,10 +758,10 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     const int WC = W * C;
     const int boundary = ip.boundary;
 
-    // LDS: [row tiles NW x G x PP][block totals NW x 64][ring (L + RB) x 64]
+    // LDS: [row tiles NW x G x PP][block totals NW x RP][ring (L + RB) x RP]
     Acc* Pt = reinterpret_cast<Acc*>(lds) + wave * G * PP;
     Acc* X = reinterpret_cast<Acc*>(lds) + NW * G * PP;
-    Acc* ring = X + NW * kWave;
+    Acc* ring = X + NW * RP;
 
     const float dc = ip.dc32;
     float wf[KT];
@@ -754,17 +847,18 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
             load_chunk_vec<Tr, NPL>(ch, rs_src, zero_row ? kDropOffset : vec_voff + rowoff, 0);
         }
     };
-    // ---------------- this lane's column ----------------
-    // Output sample oidx of the output row (the image's, or with a strided
-    // output, every ostep-th pixel compacted: the strip then covers 64 kept
-    // samples, so the row taps and the column pass run at kept columns only)
-    // and the input sample s it is centred on.
-    const int ostep = ip.step > 1 ? ip.step : 1;
+    // ---------------- this lane's columns ----------------
+    // The lane owns NC consecutive output samples oidx0 .. oidx0 + NC - 1 of
+    // the output row, centred on input samples s .. s + NC - 1.  A strided
+    // output (NC = 1) keeps every ostep-th pixel, compacted: the strip then
+    // covers 64 kept samples, so the row taps and the column pass run at
+    // kept columns only.  Every lane's samples lie inside the row tile,
+    // lanes past the end of the row included.
+    const int ostep = (NC == 1 && ip.step > 1) ? ip.step : 1;
     const int orow_len = (ostep > 1) ? (W + ostep - 1) / ostep * C : WC;
-    const int oidx = tg.o0 + lane;
-    const int s = (ostep > 1) ? (oidx / C) * ostep * C + oidx % C : oidx;
-    const bool col_live = oidx < orow_len;
-    const int colL = col_live ? s - tg.a0 : tg.off;      // tile position (lanes past the row: any inside)
+    const int oidx0 = tg.o0 + lane * NC;
+    const int s = (ostep > 1) ? (oidx0 / C) * ostep * C + oidx0 % C : oidx0;
+    const int colL = s - tg.a0;
     int tp[KT], tm[KT];
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
@@ -775,9 +869,12 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     // ---------------- column setup ----------------
     // Output rows of this task: y0 .. y0 + hs - 1, or with a strided output
     // the kept rows oq0 .. oq1 - 1 of the output image; rows outside the
-    // descriptor and columns past the row are stored to out-of-range offsets.
+    // descriptor and samples past the row are stored to out-of-range offsets.
     int oq0 = tg.y0, nrows = tg.hs;
-    const uint32_t ocol = col_live ? uint32_t(oidx * es) : kDropColumn;
+    const uint32_t ocol = (oidx0 < orow_len) ? uint32_t(oidx0 * es) : kDropColumn;
+    const bool lane_full = oidx0 + NC <= orow_len;
+    const int nlive = orow_len - oidx0;
+    const bool ovec = ip.ovec != 0;
     if (ostep > 1) {
         oq0 = (tg.y0 + ostep - 1) / ostep;
         nrows = (tg.y0 + tg.hs - 1) / ostep - oq0 + 1;
@@ -786,15 +883,55 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     const __amdgpu_buffer_rsrc_t rs_dst =
         make_rsrc(dbase, nrows > 0 ? int64_t(nrows - 1) * dstride + int64_t(orow_len) * es : 0);
     const uint32_t dstr = uint32_t(dstride);
-    // column offset (float types): the input sample at the task's first row
-    float cf = 0.0f;
+    // Float offsets.  Each group of rows subtracts one of its samples (off)
+    // and each column the input sample at the task's first row (cf); they
+    // come back through the boxes' DC gain.  Under zero extension only the
+    // samples inside the image are offset, and a box takes back the offset
+    // of its samples inside the image: dcx (along x, per lane) and dcy
+    // (along y, per output row) replace the DC gain near the borders, so
+    // outside samples still enter every sum as exact zeros.
+    const bool zext = !kInt && boundary == RSG_ZERO;
+    float cf[NC], cdc[NC], dcx[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        cf[c] = 0.0f;
+        dcx[c] = dc;
+    }
+    int off_lane = 0;                          // zext: a lane of row 0 of a group whose first sample is inside
+    uint32_t col_in = ~0u;                     // zext, border tasks: bit i = sample i of the lane's chunk inside
     if constexpr (!kInt) {
-        if (boundary != RSG_ZERO) {
-            const int yc = ext_index(tg.ybase, H, boundary);     // >= y_lo
-            cf = Tr_load_one<Tr>(rs_src, (yc - y_lo) * sstride32 + min(s, WC - 1) * es);
+        const int yc = zext ? min(max(tg.ybase, 0), H - 1) : ext_index(tg.ybase, H, boundary);   // >= y_lo
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            cf[c] = Tr_load_one<Tr>(rs_src, (yc - y_lo) * sstride32 + min(s + c, WC - 1) * es);
+        if (zext) {
+            off_lane = min(SEG - 1, max(0, (NPL - 1 - tg.a0) / NPL));
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int x = min(s + c, WC - 1) / C;
+                float d = 0.0f;
+#pragma unroll
+                for (int k = 0; k < KT; ++k)
+                    d = fmaf(wf[k], float(min(x + ip.r[k], W - 1) - max(x - ip.r[k], 0) + 1), d);
+                dcx[c] = d;
+            }
+            if constexpr (EDGE) {
+                col_in = 0;
+#pragma unroll
+                for (int i = 0; i < NPL; ++i) col_in |= (eoff[i] >= 0) ? (1u << i) : 0u;
+            }
         }
     }
-    const float cdc = cf * dc;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) cdc[c] = cf[c] * dc;
+    // zext: sum_k w_k (rows of box k inside the image) for output row y
+    auto dc_rows = [&](int y) {
+        if (y >= R && y < H - R) return dc;
+        float d = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) d = fmaf(wf[k], float(min(y + ip.r[k], H - 1) - max(y - ip.r[k], 0) + 1), d);
+        return d;
+    };
 
     auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
 #pragma unroll
@@ -818,10 +955,12 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     dropped_stores(0);
     __builtin_amdgcn_sched_barrier(0);
 
-    Acc carry = Acc(0);
+    Acc carry[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) carry[c] = Acc(0);
     int slot_m = 0;                            // ring slot of iteration m MB
     for (int m = 0; m < nsteps; ++m) {
-        Acc T[RB];
+        Acc T[RB][NC];
 #pragma unroll
         for (int g = 0; g < NGW; ++g) {
             const int b = g % PF;
@@ -832,12 +971,20 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
             }
             Acc v[NPL];
             float off = 0.0f;
+            const int yg = tg.ybase + m * MB + wave * RB + g * G;     // the group's first input row
             if constexpr (!kInt) {
-                off = (boundary == RSG_ZERO)
-                          ? 0.0f
-                          : __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(Tr::unpack(buf[b].w, 0))));
+                const uint32_t x0 = __float_as_uint(Tr::unpack(buf[b].w, 0));
+                if (zext) {
+                    off = __uint_as_float(__builtin_amdgcn_readlane(x0, off_lane));
+                    const bool row_in = unsigned(yg + jrow) < unsigned(H);
 #pragma unroll
-                for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i) - off;
+                    for (int i = 0; i < NPL; ++i)
+                        v[i] = (row_in && ((col_in >> i) & 1u)) ? Tr::unpack(buf[b].w, i) - off : 0.0f;
+                } else {
+                    off = __uint_as_float(__builtin_amdgcn_readfirstlane(x0));
+#pragma unroll
+                    for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i) - off;
+                }
             } else {
 #pragma unroll
                 for (int i = 0; i < NPL; ++i) v[i] = Tr::unpack(buf[b].w, i);
@@ -865,58 +1012,84 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
             }
             wave_lds_fence();
             // row box differences (Eq. indep), lane = column; floats add the
-            // group offset's share
-            float init = 0.0f;
-            if constexpr (!kInt) init = off * dc;
+            // group offset's share (none for rows outside the image)
+            float od[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) od[c] = off * dcx[c];
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 const Acc* Pj = Pt + j * PP;
-                Acc t;
-                if constexpr (kInt) {
-                    t = 0;
+                const bool jin = !zext || unsigned(yg + j) < unsigned(H);
 #pragma unroll
-                    for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k]] - Pj[tm[k]]);
-                } else {
-                    t = fmaf(wf[0], Pj[tp[0]] - Pj[tm[0]], init);
+                for (int c = 0; c < NC; ++c) {
+                    const float init = jin ? od[c] : 0.0f;
+                    Acc t;
+                    if constexpr (kInt) {
+                        t = 0;
 #pragma unroll
-                    for (int k = 1; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k]] - Pj[tm[k]], t);
+                        for (int k = 0; k < KT; ++k) t += __umul24(wm[k], Pj[tp[k] + c] - Pj[tm[k] + c]);
+                    } else {
+                        t = fmaf(wf[0], Pj[tp[0] + c] - Pj[tm[0] + c], init);
+#pragma unroll
+                        for (int k = 1; k < KT; ++k) t = fmaf(wf[k], Pj[tp[k] + c] - Pj[tm[k] + c], t);
+                    }
+                    T[g * G + j][c] = t;
                 }
-                T[g * G + j] = t;
             }
         }
 
         // ---- column running sums of the block (Eq. alg1), then its carry ----
         {   // T becomes the block's running sums J
-            Acc run = Acc(0);
+            Acc run[NC];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                if constexpr (kInt) run += T[i];
-                else run += T[i] - cf;
-                T[i] = run;
+            for (int c = 0; c < NC; ++c) {
+                run[c] = Acc(0);
+#pragma unroll
+                for (int i = 0; i < RB; ++i) {
+                    if constexpr (kInt) {
+                        run[c] += T[i][c];
+                    } else {
+                        const bool iin = !zext || unsigned(tg.ybase + m * MB + wave * RB + i) < unsigned(H);
+                        run[c] += T[i][c] - (iin ? cf[c] : 0.0f);
+                    }
+                    T[i][c] = run[c];
+                }
             }
-            X[wave * kWave + lane] = run;
+            lds_put<Acc, NC>(X + wave * RP + lane * NC, run);
         }
         __syncthreads();
-        Acc cw = carry;
+        Acc cw[NC];
         {
-            Acc acc = carry;
+            Acc acc[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                acc[c] = carry[c];
+                cw[c] = carry[c];
+            }
 #pragma unroll
             for (int v = 0; v < NW; ++v) {
-                cw = (v == wave) ? acc : cw;
-                acc += X[v * kWave + lane];
+                Acc xv[NC];
+                lds_get<Acc, NC>(X + v * RP + lane * NC, xv);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    cw[c] = (v == wave) ? acc[c] : cw[c];
+                    acc[c] += xv[c];
+                }
             }
-            carry = acc;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) carry[c] = acc[c];
         }
         int sb = slot_m + wave * RB;
         sb -= (sb >= L) ? L : 0;
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-            T[i] = cw + T[i];
-            ring[(sb + i) * RP + lane] = T[i];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) T[i][c] = cw[c] + T[i][c];
+            lds_put<Acc, NC>(ring + (sb + i) * RP + lane * NC, T[i]);
         }
         if (sb == 0) {                         // slots 0 .. RB-1 also live at L .. L+RB-1
 #pragma unroll
-            for (int i = 0; i < RB; ++i) ring[(L + i) * RP + lane] = T[i];
+            for (int i = 0; i < RB; ++i) lds_put<Acc, NC>(ring + (L + i) * RP + lane * NC, T[i]);
         }
         __syncthreads();
 
@@ -950,49 +1123,58 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
                 if (++rr == ostep) { rr = 0; ++qrow; }
             }
         }
-        auto combine_store = [&](const Acc (&rv)[2 * KT], int i) {
+        // the lane's NC results of block row i from its taps rv, stored
+        auto combine_store = [&](const Acc (&rv)[2 * KT][NC], int i) {
             const int vo = int(ocol + uint32_t(soff[i]));
-            if constexpr (kInt) {
-                uint64_t U = 0;
+            const float dcy = zext ? dc_rows(tg.y0 + kb + i) : dc;
+            uint32_t w[NC];
 #pragma unroll
-                for (int k2 = 0; k2 < KT; ++k2) U += uint64_t(wm[k2]) * uint64_t(rv[2 * k2] - rv[2 * k2 + 1]);
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, vo, 0, 0);
-            } else {
-                float o = cdc;
+            for (int c = 0; c < NC; ++c) {
+                if constexpr (kInt) {
+                    uint64_t U = 0;
 #pragma unroll
-                for (int k2 = 0; k2 < KT; ++k2) o = fmaf(wf[k2], rv[2 * k2] - rv[2 * k2 + 1], o);
-                store_out<Tr>(rs_dst, vo, 0, o);
+                    for (int k2 = 0; k2 < KT; ++k2)
+                        U += uint64_t(wm[k2]) * uint64_t(rv[2 * k2][c] - rv[2 * k2 + 1][c]);
+                    w[c] = exact_round_div(U, ip);
+                } else {
+                    float o = zext ? cf[c] * dcy : cdc[c];
+#pragma unroll
+                    for (int k2 = 0; k2 < KT; ++k2) o = fmaf(wf[k2], rv[2 * k2][c] - rv[2 * k2 + 1][c], o);
+                    w[c] = out_bits<Tr>(o);
+                }
             }
+            store_group<Tr, NC>(rs_dst, vo, w, lane_full, nlive, ovec);
         };
         if (ostep == 1) {
-            // every row: the taps of half a block at a time (fewer live registers)
-            constexpr int HB = RB / 2;
+            // every row: the taps of HB rows at a time (fewer live registers)
+            constexpr int HB = (8 * KT * NC <= 48) ? 4 : ((4 * KT * NC <= 48) ? 2 : 1);
+            static_assert(RB % HB == 0, "whole sub-blocks");
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < RB / HB; ++h) {
                 __builtin_amdgcn_sched_barrier(0);
-                Acc rv[HB][2 * KT];
+                Acc rv[HB][2 * KT][NC];
 #pragma unroll
                 for (int k = 0; k < KT; ++k) {
 #pragma unroll
                     for (int i = 0; i < HB; ++i) {
-                        rv[i][2 * k] = ring[(ta[k] + h * HB + i) * RP + lane];
-                        rv[i][2 * k + 1] = ring[(tb[k] + h * HB + i) * RP + lane];
+                        lds_get<Acc, NC>(ring + (ta[k] + h * HB + i) * RP + lane * NC, rv[i][2 * k]);
+                        lds_get<Acc, NC>(ring + (tb[k] + h * HB + i) * RP + lane * NC, rv[i][2 * k + 1]);
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < HB; ++i) combine_store(rv[i], h * HB + i);
             }
-        } else {
+        } else if constexpr (NC == 1) {
             // strided output: only kept rows read their taps and combine (a
             // uniform test); a dropped row still issues one store, out of range
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 if (soff[i] != kDropOffset) {
-                    Acc rv[2 * KT];
+                    Acc rv[2 * KT][NC];
 #pragma unroll
                     for (int k = 0; k < KT; ++k) {
-                        rv[2 * k] = ring[(ta[k] + i) * RP + lane];
-                        rv[2 * k + 1] = ring[(tb[k] + i) * RP + lane];
+                        rv[2 * k][0] = ring[(ta[k] + i) * RP + lane];
+                        rv[2 * k + 1][0] = ring[(tb[k] + i) * RP + lane];
                     }
                     combine_store(rv, i);
                 } else {
@@ -1006,9 +1188,10 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     }
 }
 
-// One task: 64 sample-columns x hs output rows of image `ip`, on one wave
-// (CO = false) or on a workgroup of kCoWaves waves (CO = true).
-template <class Tr, int C, int SEG, int NPL, int KT, bool CO = false>
+// One task: 64 NC sample-columns x hs output rows of image `ip`, on one
+// wave (CO = false, NC = 1) or on a workgroup of kCoWaves waves (CO = true)
+// whose lanes own NC consecutive columns each.
+template <class Tr, int C, int SEG, int NPL, int KT, bool CO = false, int NC = 1>
 __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t* lds)
 {
     constexpr int G = kWave / SEG;
@@ -1025,7 +1208,7 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
     // the one-wave form starts pre < G rows earlier, so that emission starts
     // on a group boundary; the cooperative form emits per row
     const int pre = CO ? 0 : (G - (2 * ip.R + 1) % G) % G;
-    tg.s0 = strip * kWave;
+    tg.s0 = strip * kWave * NC;
     tg.o0 = tg.s0;
     if (CO && ip.step > 1) {                   // a strip of 64 kept output samples: its first input sample
         tg.s0 = (tg.o0 / C) * ip.step * C + tg.o0 % C;
@@ -1040,8 +1223,8 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
     const int WC = ip.W * C;
     const bool interior = ip.vec && tg.a0 >= 0 && tg.a0 + SEG * NPL <= WC;
     if constexpr (CO) {
-        if (interior) stream_task_co<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
-        else stream_task_co<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
+        if (interior) stream_task_co<Tr, C, SEG, NPL, KT, false, NC>(ip, tg, lds);
+        else stream_task_co<Tr, C, SEG, NPL, KT, true, NC>(ip, tg, lds);
     } else {
         if (interior) stream_task<Tr, C, SEG, NPL, KT, false>(ip, tg, lds);
         else stream_task<Tr, C, SEG, NPL, KT, true>(ip, tg, lds);
@@ -1061,11 +1244,11 @@ __device__ __forceinline__ int xcd_task(int b, int n)
 }
 
 // One task per workgroup of kCoWaves waves (the cooperative form).
-template <class Tr, int C, int SEG, int NPL, int KT>
+template <class Tr, int C, int SEG, int NPL, int KT, int NC>
 __global__ __launch_bounds__(kCoWaves * kWave) void k_single_co(ImgParams ip)
 {
     extern __shared__ uint32_t lds[];
-    run_task<Tr, C, SEG, NPL, KT, true>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
+    run_task<Tr, C, SEG, NPL, KT, true, NC>(ip, xcd_task(blockIdx.x, ip.ntasks), lds);
 }
 
 template <class Tr, int C, int SEG, int NPL, int KT>
@@ -1102,7 +1285,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // Persistent batch kernel, cooperative form: each workgroup pops (image,
 // task) items and runs them on its kCoWaves waves.  LDS word 0 carries the
 // popped index to every wave; the task's LDS starts 16 bytes later.
-template <class Tr, int C, int KT, int S0, int N0, int S1, int N1, int S2, int N2, int S3, int N3>
+template <class Tr, int C, int KT, int NC, int S0, int N0, int S1, int N1, int S2, int N2, int S3, int N3>
 __global__ __launch_bounds__(kCoWaves * kWave) void k_batch_co(const ImgParams* __restrict__ imgs,
                                                               const BatchTask* __restrict__ tasks, int ntasks,
                                                               unsigned* __restrict__ counter)
@@ -1116,10 +1299,10 @@ __global__ __launch_bounds__(kCoWaves * kWave) void k_batch_co(const ImgParams* 
         if (t >= unsigned(ntasks)) break;                  // the same for every wave
         const BatchTask bt = tasks[t];
         const ImgParams& ip = imgs[bt.img];
-        if (ip.seg == S0 && ip.npl == N0) run_task<Tr, C, S0, N0, KT, true>(ip, bt.task, tl);
-        else if (ip.seg == S1 && ip.npl == N1) run_task<Tr, C, S1, N1, KT, true>(ip, bt.task, tl);
-        else if (ip.seg == S2 && ip.npl == N2) run_task<Tr, C, S2, N2, KT, true>(ip, bt.task, tl);
-        else if (ip.seg == S3 && ip.npl == N3) run_task<Tr, C, S3, N3, KT, true>(ip, bt.task, tl);
+        if (ip.seg == S0 && ip.npl == N0) run_task<Tr, C, S0, N0, KT, true, NC>(ip, bt.task, tl);
+        else if (ip.seg == S1 && ip.npl == N1) run_task<Tr, C, S1, N1, KT, true, NC>(ip, bt.task, tl);
+        else if (ip.seg == S2 && ip.npl == N2) run_task<Tr, C, S2, N2, KT, true, NC>(ip, bt.task, tl);
+        else if (ip.seg == S3 && ip.npl == N3) run_task<Tr, C, S3, N3, KT, true, NC>(ip, bt.task, tl);
         __syncthreads();                                   // every wave is done with the slot and the tiles
     }
 }

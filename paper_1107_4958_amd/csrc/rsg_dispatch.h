@@ -29,7 +29,9 @@ template <class Tr, int C, int SEG, int NPL, int KT>
 int launch_one(const ImgParams& ip, hipStream_t st)
 {
     if (ip.co) {
-        auto fn = dev::k_single_co<Tr, C, SEG, NPL, KT>;
+        constexpr int NCW = wide_nc(C);
+        if (ip.nc != 1 && ip.nc != NCW) return set_error(RSG_EINVAL, "no kernel for %d columns per lane", ip.nc);
+        auto fn = (ip.nc == NCW) ? dev::k_single_co<Tr, C, SEG, NPL, KT, NCW> : dev::k_single_co<Tr, C, SEG, NPL, KT, 1>;
         int rc = set_lds_limit(reinterpret_cast<const void*>(fn), ip.lds_bytes);
         if (rc != RSG_OK) return rc;
         hipLaunchKernelGGL(fn, dim3(ip.ntasks), dim3(kCoWaves * kWave), ip.lds_bytes, st, ip);
@@ -86,8 +88,12 @@ int batch_one(const BatchClassLaunch& b, hipStream_t st)
 {
     using Lo = Layouts<C>;
     if (b.co) {
-        auto fn = dev::k_batch_co<Tr, C, KT, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2], Lo::N[2], Lo::S[3],
-                                  Lo::N[3]>;
+        constexpr int NCW = wide_nc(C);
+        if (b.nc != 1 && b.nc != NCW) return set_error(RSG_EINVAL, "no batch kernel for %d columns per lane", b.nc);
+        auto fn = (b.nc == NCW) ? dev::k_batch_co<Tr, C, KT, NCW, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2],
+                                                  Lo::N[2], Lo::S[3], Lo::N[3]>
+                                : dev::k_batch_co<Tr, C, KT, 1, Lo::S[0], Lo::N[0], Lo::S[1], Lo::N[1], Lo::S[2],
+                                                  Lo::N[2], Lo::S[3], Lo::N[3]>;
         int rc = set_lds_limit(reinterpret_cast<const void*>(fn), b.lds);
         if (rc != RSG_OK) return rc;
         hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kCoWaves * kWave), b.lds, st, b.d_imgs, b.d_tasks, b.ntasks,

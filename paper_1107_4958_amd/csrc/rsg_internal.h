@@ -30,6 +30,11 @@ constexpr int kPrefetch = RSG_PREFETCH;   // groups of row loads in flight per w
 constexpr int kCoWaves = 4;        // waves per task of the cooperative fused form
 constexpr int kCoRows = 8;         // rows per wave per step of the cooperative form
 constexpr int kCoStep = kCoWaves * kCoRows;   // rows per step
+// Columns per lane of the cooperative form on unstrided outputs: a task is
+// 64 pixels wide for C = 3 (a lane owns one pixel's channels) and 128
+// samples wide for C = 1, which shortens the row span per output sample and
+// lets one vector access carry a lane's columns.
+constexpr int wide_nc(int C) { return C == 1 ? 2 : (C == 3 ? 3 : 1); }
 constexpr int64_t kOffsetLimit = int64_t(1) << 30;   // every byte offset a task touches stays below this
 
 // Everything one image's kernel needs; plain data, copied to the device for
@@ -71,6 +76,8 @@ struct ImgParams {
     int32_t nslices;               // fused path: a stack of this many equal images (<= 1: one image)
     int64_t slice_stride;          // elements from one image of the stack to the next (source and destination)
     int32_t co;                    // fused path: 1 = cooperative workgroups of kCoWaves waves, 0 = one wave
+    int32_t nc;                    // cooperative form: consecutive columns per lane (1, or wide_nc(C))
+    int32_t ovec;                  // the destination allows one vector store per lane's columns
     int32_t pnpl[2];               // samples per lane of pass A, pass B
     int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
     uint32_t plds[2];              // LDS bytes per workgroup of pass A, pass B
@@ -136,6 +143,9 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step = 1, int hs_pref
 void set_hs_override(int hs);
 // Process-wide path override (0: planner's choice, 1: fused, 2: two-pass).
 void set_path_override(int path);
+// Process-wide columns-per-lane override of the cooperative form (0: none,
+// 1: one, > 1: wide_nc(C)).
+void set_nc_override(int nc);
 
 // Launchers (rsg_kernels.hip).
 int launch_single(const ImgParams& ip, hipStream_t stream);
@@ -182,6 +192,7 @@ inline uint32_t pass_lds_bytes(int npl, int hw, int stages, int tr = kPassRowsHo
 struct BatchClassLaunch {
     int dtype, C, kt;
     int co;                        // 1: cooperative workgroups (LDS includes the task slot)
+    int nc;                        // cooperative form: columns per lane
     int grid;
     uint32_t lds;
     const ImgParams* d_imgs;
@@ -211,11 +222,11 @@ inline void scan_layout(int C, int i, int* seg, int* npl)
 // column ring keeps the dense 64-word pitch (one word per lane).
 constexpr int row_tile_pitch(int seg, int npl) { return seg * npl + 32; }
 // Cooperative form: one row tile per wave, one block total per wave and
-// column, and the ring of Lco + kCoRows rows.
-inline uint32_t tile_lds_bytes_co(int seg, int npl, int Lco)
+// column, and the ring of Lco + kCoRows rows (64 nc columns).
+inline uint32_t tile_lds_bytes_co(int seg, int npl, int Lco, int nc)
 {
     const int G = kWave / seg;
-    return uint32_t(4 * (kCoWaves * G * row_tile_pitch(seg, npl) + kCoWaves * kWave + (Lco + kCoRows) * kWave));
+    return uint32_t(4 * (kCoWaves * G * row_tile_pitch(seg, npl) + (kCoWaves + Lco + kCoRows) * kWave * nc));
 }
 // Two row tiles (double-buffered) and the ring of L + G rows.
 inline uint32_t tile_lds_bytes(int seg, int npl, int L)

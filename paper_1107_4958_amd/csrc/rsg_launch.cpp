@@ -136,7 +136,7 @@ int launch_batch_class(const BatchClassLaunch& b, hipStream_t stream)
 namespace {
 constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
-constexpr int kMaxClasses = 4 * 4 * 3;   // dtype x C x taps
+constexpr int kMaxClasses = 4 * 4 * 3 * 2;   // dtype x C x taps x (one or wide_nc(C) columns per lane)
 }  // namespace
 
 int64_t pass_blocks(const ImgParams* imgs, int nimg)
@@ -179,10 +179,10 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
     if (ws_bytes < need) return set_error(RSG_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, need);
 
     // fused images: group the tasks by kernel class, keeping their order
-    std::map<std::tuple<int, int, int, int>, std::vector<BatchTask>> classes;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<BatchTask>> classes;
     for (int t = 0; t < ntasks; ++t) {
         const ImgParams& ip = h_imgs[h_tasks[t].img];
-        classes[std::make_tuple(ip.dtype, ip.C, ip.kt, ip.co)].push_back(h_tasks[t]);
+        classes[std::make_tuple(ip.dtype, ip.C, ip.kt, ip.co, ip.co ? ip.nc : 1)].push_back(h_tasks[t]);
     }
 
     // two-pass images: intermediates after the header, pass parameters 2j
@@ -252,6 +252,7 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
         b.C = std::get<1>(kv.first);
         b.kt = std::get<2>(kv.first);
         b.co = std::get<3>(kv.first);
+        b.nc = std::get<4>(kv.first);
         b.lds = 0;
         for (const BatchTask& t : kv.second) {
             const ImgParams& ip = h_imgs[t.img];

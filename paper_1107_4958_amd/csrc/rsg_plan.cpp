@@ -34,16 +34,19 @@ constexpr uint32_t kLdsLimit = 160u * 1024u;    // gfx950: 160 KiB of LDS per CU
 int gcd_i(int a, int b) { while (b) { int t = a % b; a = b; b = t; } return a; }
 int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
 
-// Tuning table (text): lines "dtype C rlo rhi nlo nhi hs", '#' starts a
-// comment.  An image of dtype and channel count C whose largest half-width R
-// lies in [rlo, rhi] and whose work size n = strips * H (strips of 64
+// Tuning table (text): lines "dtype C rlo rhi nlo nhi hs [nc]", '#' starts
+// a comment.  An image of dtype and channel count C whose largest half-width
+// R lies in [rlo, rhi] and whose work size n = strips * H (strips of 64
 // samples) lies in [nlo, nhi] takes the fused kernel with segment height hs
-// from the first matching line, or the two-pass path if hs is -1.
-struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs; };
+// from the first matching line, or the two-pass path if hs is -1; nc > 1
+// selects the wide column form (wide_nc(C) columns per lane), 1 one column
+// per lane, 0 or none the built-in rule.
+struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs, nc; };
 std::once_flag g_tune_once;
 std::vector<TuneEntry> g_tune;
 std::atomic<int> g_hs_override{0};
 std::atomic<int> g_path_override{0};
+std::atomic<int> g_nc_override{0};
 
 // Two-pass geometry: the smallest chunk (64 NPL samples) that holds the
 // window head (2R + 1) C and fits the LDS with one staging tile (0 if none
@@ -79,12 +82,14 @@ void load_tune_table()
         if (h != std::string::npos) line.resize(h);
         std::istringstream is(line);
         TuneEntry e;
-        if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.nlo >> e.nhi >> e.hs && (e.hs > 0 || e.hs == -1))
+        if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.nlo >> e.nhi >> e.hs && (e.hs > 0 || e.hs == -1)) {
+            if (!(is >> e.nc) || e.nc < 0) e.nc = 0;
             g_tune.push_back(e);
+        }
     }
 }
 
-bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs)
+bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs, int* nc)
 {
     const int ov = g_hs_override.load(std::memory_order_relaxed);
     if (ov > 0) { *hs = ov; return true; }
@@ -92,6 +97,7 @@ bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs)
     for (const auto& e : g_tune)
         if (e.dtype == dtype && e.C == C && R >= e.rlo && R <= e.rhi && n >= e.nlo && n <= e.nhi) {
             *hs = e.hs;
+            *nc = e.nc;
             return true;
         }
     return false;
@@ -140,6 +146,7 @@ int check_boxes(const rsg_boxes& b, bool need_u8)
 
 void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_order_relaxed); }
 void set_path_override(int path) { g_path_override.store(path, std::memory_order_relaxed); }
+void set_nc_override(int nc) { g_nc_override.store(nc > 0 ? nc : 0, std::memory_order_relaxed); }
 
 int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
 {
@@ -228,8 +235,8 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1, p.pst[1], p.ptr[1]);
     }
     const int ov = g_path_override.load(std::memory_order_relaxed);
-    int hs_t = 0;
-    const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t);
+    int hs_t = 0, nc_t = 0;
+    const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t, &nc_t);
     bool two = two_ok && (tabled ? hs_t < 0 : R * C >= kTwoPassMinRC);
     if (ov == 1 || ov == 3) two = false;
     // strided output: the fused two-wave form (which stores every step-th row
@@ -240,24 +247,38 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     }
 
     // ---- row-scan layout: first (lanes per row, samples per lane) whose
-    //      segment covers the row span [s0 - (R+1)C, s_63 + RC] of a task's
-    //      64 columns s_0 .. s_63 (consecutive samples; with a strided
-    //      output, the input samples of 64 consecutive kept samples) ----
-    int64_t cols = kWave;
-    if (step > 1) {
-        int64_t np = 0;                              // pixels a strip of 64 kept samples spans
-        for (int k = 0; k < C; ++k) np = std::max<int64_t>(np, ((kWave * k) % C + kWave - 1) / C + 1);
-        cols = ((np - 1) * step + 1) * C;
-    }
-    int seg = 0, npl = 0, align = 1;
-    for (int i = 0; i < kLayouts && !seg; ++i) {
-        int sg, n;
-        scan_layout(C, i, &sg, &n);
-        const int cb = n * es;                       // chunk bytes
-        const int unit = gcd_i(cb, 16);              // vector load granule
-        const int al = lcm_i(C, std::max(1, unit / es));
-        const int64_t span = cols + int64_t(2 * R + 1) * C + al - 1;
-        if (span <= int64_t(sg) * n) { seg = sg; npl = n; align = al; }
+    //      segment covers the row span [s0 - (R+1)C, s_last + RC] of a
+    //      task's columns s0 .. s_last: 64 nc consecutive samples, or with a
+    //      strided output the input samples of 64 consecutive kept samples.
+    //      The cooperative form takes nc = wide_nc(C) columns per lane where
+    //      the span and the LDS allow, else one. ----
+    // single launches, batches and served images run the cooperative form
+    // (kCoWaves waves per task); path override 3 selects the one-wave form
+    const int co = (ov == 3) ? 0 : 1;
+    int seg = 0, npl = 0, align = 1, nc = 1;
+    // columns per lane: the override, else the table, else one
+    const int nc_ov = g_nc_override.load(std::memory_order_relaxed);
+    const int nc_want = nc_ov > 0 ? nc_ov : (nc_t > 0 ? nc_t : 1);
+    const int nc_first = (co && step == 1 && nc_want > 1) ? wide_nc(C) : 1;
+    const int Lco = (kCoStep + 2 * R + 1 + kCoRows - 1) / kCoRows * kCoRows;
+    for (int nci = nc_first; nci >= 1 && !seg; nci = (nci > 1) ? 1 : 0) {
+        int64_t cols = int64_t(kWave) * nci;
+        if (step > 1) {
+            int64_t np = 0;                          // pixels a strip of 64 kept samples spans
+            for (int k = 0; k < C; ++k) np = std::max<int64_t>(np, ((kWave * k) % C + kWave - 1) / C + 1);
+            cols = ((np - 1) * step + 1) * C;
+        }
+        for (int i = 0; i < kLayouts && !seg; ++i) {
+            int sg, n;
+            scan_layout(C, i, &sg, &n);
+            const int cb = n * es;                   // chunk bytes
+            const int unit = gcd_i(cb, 16);          // vector load granule
+            const int al = lcm_i(C, std::max(1, unit / es));
+            const int64_t span = cols + int64_t(2 * R + 1) * C + al - 1;
+            if (span > int64_t(sg) * n) continue;
+            if (nci > 1 && tile_lds_bytes_co(sg, n, Lco, nci) + 4u * kBatchSlotWords > kLdsLimit) break;
+            seg = sg; npl = n; align = al; nc = nci;
+        }
     }
     if (!seg && !two) {
         if (two_ok && ov != 1 && ov != 3) {
@@ -291,19 +312,24 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     }
     p.G = kWave / seg;
     p.L = (2 * R + 1 + p.G + p.G - 1) / p.G * p.G;
-    p.Lco = (kCoStep + 2 * R + 1 + kCoRows - 1) / kCoRows * kCoRows;
-    // single launches, batches and served images run the cooperative form
-    // (kCoWaves waves per task); path override 3 selects the one-wave form
-    p.co = (ov == 3) ? 0 : 1;
+    p.Lco = Lco;
+    p.co = co;
+    p.nc = nc;
+    {   // vector stores of a lane's columns: 2-byte and 1-byte elements need
+        // the destination rows aligned to the group (4-byte ones: to the element)
+        const int gb = nc * es;
+        const uintptr_t da = reinterpret_cast<uintptr_t>(d.dst);
+        p.ovec = (es == 4) || (nc > 1 && (gb & (gb - 1)) == 0 && da % gb == 0 && (ds * es) % gb == 0);
+    }
     p.lds_one = tile_lds_bytes(seg, npl, p.L);
-    p.lds_bytes = p.co ? tile_lds_bytes_co(seg, npl, p.Lco) : p.lds_one;
+    p.lds_bytes = p.co ? tile_lds_bytes_co(seg, npl, p.Lco, p.nc) : p.lds_one;
     {   // the batch kernel of the cooperative form adds its task slot
         const uint32_t need = std::max(p.lds_bytes + (p.co ? 4u * kBatchSlotWords : 0u), p.lds_one);
         if (need > kLdsLimit)
             return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", need, kLdsLimit);
     }
-    // a strip is 64 output samples (strided: 64 kept samples)
-    p.nstrips = int((WoC + kWave - 1) / kWave);
+    // a strip is 64 nc output samples (strided: 64 kept samples)
+    p.nstrips = int((WoC + int64_t(kWave) * nc - 1) / (int64_t(kWave) * nc));
 
     // ---- segment height ----
     int hs = hs_pref > 0 ? hs_pref : ((tabled && hs_t > 0) ? hs_t : default_hs(d.H, p.nstrips, R, p.lds_bytes));

@@ -23,13 +23,26 @@ def _desc(H, W, C=1, dt=rsg.RSG_F32, sigma=8.0, K=3, stride=0):
 def test_plan_shape_basics():
     hs, tasks, lds = rsg.rsg_plan_shape(_desc(4096, 4096))
     assert 1 <= hs <= 4096 and lds > 0
-    assert tasks == 64 * -(-4096 // hs)             # 64-sample strips x segments
     try:
+        rsg.rsg_tune_columns(1)
+        hs, tasks, lds = rsg.rsg_plan_shape(_desc(4096, 4096))
+        assert tasks == 64 * -(-4096 // hs)         # 64-sample strips x segments
+        # the wide form: lanes own two columns at C = 1 and one pixel (three
+        # samples) at C = 3, strips of 128 and 192 samples
+        rsg.rsg_tune_columns(2)
+        hs2, tasks2, lds2 = rsg.rsg_plan_shape(_desc(4096, 4096))
+        assert tasks2 == 32 * -(-4096 // hs2) and lds2 > lds
         rsg.rsg_tune_path(rsg.RSG_PATH_FUSED)
         hs3, tasks3, _ = rsg.rsg_plan_shape(_desc(100, 70, C=3, dt=rsg.RSG_U8))
+        assert tasks3 == -(-210 // 192) * -(-100 // hs3)
+        rsg.rsg_tune_columns(1)
+        hs3, tasks3, _ = rsg.rsg_plan_shape(_desc(100, 70, C=3, dt=rsg.RSG_U8))
         assert tasks3 == -(-210 // 64) * -(-100 // hs3)
+        with pytest.raises(rsg.RsgError):
+            rsg.rsg_tune_columns(-1)
     finally:
         rsg.rsg_tune_path(rsg.RSG_PATH_AUTO)
+        rsg.rsg_tune_columns(0)
     hs3, tasks3, _ = rsg.rsg_plan_shape(_desc(100, 70, C=3, dt=rsg.RSG_U8))
     if hs3 == 100:                                  # two passes: workgroups of 16 rows in each
         assert tasks3 == -(-100 // 16) + -(-210 // 16)
