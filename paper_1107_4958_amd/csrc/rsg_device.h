@@ -217,25 +217,26 @@ __device__ __forceinline__ void load_chunk_elem(Chunk<Tr, NPL>& ch, __amdgpu_buf
 }
 
 // uint8 output: round half up of U / G^2, exactly, in integer arithmetic.
-// N = U + floor(G^2 / 2) < 256 G^2 <= 2^56.  N >> qsh (qsh per image: the
-// shift that brings 256 G^2 below 2^32) converts to FP32 in one instruction;
-// scaled by invG2s = 2^qsh / G^2 it is within 2^-13 of N / G^2 (the dropped
-// bits are below 2^-23 of G^2 and three roundings of 2^-24 each on a value
-// below 256 stay under 2^-15), so the estimate lowered by a margin of 2^-11
-// truncates to q or q - 1, and one comparison of N with (q + 1) G^2 (a 64-bit
-// multiply-add, G^2 < 2^48) decides.
-__device__ __forceinline__ uint32_t exact_round_div_u(uint64_t U, uint64_t G2, uint64_t G2half, float invG2s, int qsh)
+// The caller accumulates N = U + floor(G^2 / 2) < 256 G^2 <= 2^56 (the sum
+// starts at floor(G^2 / 2)); the result is Q = floor(N / G^2).  N >> qsh
+// (qsh per image: the shift that brings 256 G^2 below 2^32) converts to FP32
+// in one instruction; scaled by invG2s = 2^qsh / G^2 it is within 2^-13 of
+// N / G^2 (the dropped bits are below 2^-23 of G^2, and three roundings of
+// 2^-24 relative on a value below 257 stay under 2^-15).  So N / G^2 + 1 -
+// 2^-11, estimated, truncates to Q + 1 or Q and is never negative, and one
+// comparison of N with that candidate times G^2 (a 64-bit product, G^2 <
+// 2^48) decides.
+__device__ __forceinline__ uint32_t round_quotient(uint64_t N, uint64_t G2, float invG2s, int qsh)
 {
-    const uint64_t N = U + G2half;
     const float nf = float(uint32_t(N >> qsh));
-    const uint32_t q = uint32_t(fmaxf(fmaf(nf, invG2s, -0.00048828125f), 0.0f));
-    uint64_t P1 = uint64_t(q) * uint64_t(uint32_t(G2)) + G2;       // (q + 1) G^2, low word product
-    P1 += uint64_t(__umul24(q, uint32_t(G2 >> 32))) << 32;
-    return q + ((N >= P1) ? 1u : 0u);
+    const uint32_t q1 = uint32_t(fmaf(nf, invG2s, 1.0f - 0.00048828125f));
+    uint64_t P = uint64_t(q1) * uint64_t(uint32_t(G2));
+    P += uint64_t(__umul24(q1, uint32_t(G2 >> 32))) << 32;
+    return q1 - ((N < P) ? 1u : 0u);
 }
-__device__ __forceinline__ uint32_t exact_round_div(uint64_t U, const ImgParams& ip)
+__device__ __forceinline__ uint32_t round_quotient(uint64_t N, const ImgParams& ip)
 {
-    return exact_round_div_u(U, ip.G2, ip.G2half, ip.invG2, ip.qsh);
+    return round_quotient(N, ip.G2, ip.invG2, ip.qsh);
 }
 
 // One element at byte offset `boff` of a buffer, as float.
@@ -622,10 +623,10 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
             const int voff = int(og + uint32_t(j) * dstr);
             if constexpr (kInt) {
                 // U = sum m_k D_k < 256 G^2: exact in uint64
-                uint64_t U = 0;
+                uint64_t N = ip.G2half;
 #pragma unroll
-                for (int k = 0; k < KT; ++k) U += uint64_t(wm[k]) * uint64_t(rv[j][2 * k] - rv[j][2 * k + 1]);
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(exact_round_div(U, ip)), rs_dst, voff, 0, 0);
+                for (int k = 0; k < KT; ++k) N += uint64_t(wm[k]) * uint64_t(rv[j][2 * k] - rv[j][2 * k + 1]);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(round_quotient(N, ip)), rs_dst, voff, 0, 0);
             } else {
                 float o = c2dc;
 #pragma unroll
@@ -774,11 +775,16 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     const int64_t sstride = ip.src_stride * es;
     const int64_t dstride = ip.dst_stride * es;
     const int nsteps = (tg.niter + MB - 1) / MB;
+    [[maybe_unused]] const uint64_t G2 = ip.G2, G2half = ip.G2half;   // uint8 rounding
+    [[maybe_unused]] const float invG2 = ip.invG2;
+    [[maybe_unused]] const int qsh = ip.qsh;
 
     // ---------------- row-pass setup ----------------
     const int jrow = lane / SEG;
     const int q = lane % SEG;
     const int y_lo = max(0, tg.ybase);
+    // groups whose rows all lie in [y_lo, H) start at y_lo + [0, fast_n)
+    const int fast_n = max(0, H - G - y_lo + 1);
     const char* sbase = reinterpret_cast<const char*>(ip.src) + tg.slice_off + int64_t(y_lo) * sstride;
     const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(H - 1 - y_lo) * sstride + int64_t(WC) * es);
     const int cs = tg.a0 + NPL * q;
@@ -815,7 +821,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     auto load = [&](Chunk<Tr, NPL>& ch, Chunk<Tr, NPL>& ech, int gq) {
         const int it = (gq / NGW) * MB + wave * RB + (gq % NGW) * G;
         const int yg = tg.ybase + it;
-        if (yg >= y_lo && yg + G <= H) {
+        if (unsigned(yg - y_lo) < unsigned(fast_n)) {
             const int soff = (yg - y_lo) * sstride32;
             if constexpr (kSplit) {
                 load_chunk_vec<Tr, NPL>(ch, rs_src, fast_vec, soff);
@@ -1107,10 +1113,11 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
         const int kb = m * MB + wave * RB - tg.emit0;
         int soff[RB];
         if (ostep == 1) {
+            uint32_t ob = uint32_t(kb) * dstr;
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
-                const int k = kb + i;
-                soff[i] = (k >= 0 && k < tg.hs) ? int(uint32_t(k) * dstr) : kDropOffset;
+                soff[i] = (unsigned(kb + i) < unsigned(tg.hs)) ? int(ob) : kDropOffset;
+                ob += dstr;
             }
         } else {
             const int yb = tg.y0 + kb;
@@ -1131,11 +1138,11 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if constexpr (kInt) {
-                    uint64_t U = 0;
+                    uint64_t N = G2half;
 #pragma unroll
                     for (int k2 = 0; k2 < KT; ++k2)
-                        U += uint64_t(wm[k2]) * uint64_t(rv[2 * k2][c] - rv[2 * k2 + 1][c]);
-                    w[c] = exact_round_div(U, ip);
+                        N += uint64_t(wm[k2]) * uint64_t(rv[2 * k2][c] - rv[2 * k2 + 1][c]);
+                    w[c] = round_quotient(N, G2, invG2, qsh);
                 } else {
                     float o = zext ? cf[c] * dcy : cdc[c];
 #pragma unroll

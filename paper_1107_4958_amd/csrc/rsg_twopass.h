@@ -230,10 +230,10 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
                 for (int kk = 0; kk < KT; ++kk) s += __umul24(wm[kk], win[o + tp[kk]] - win[o + tm[kk]]);
                 word = s;
             } else if constexpr (OUT == kOutU8) {
-                uint64_t U = 0;                       // exact: see the fused kernel
+                uint64_t N = p.G2half;                // exact: see the fused kernel
 #pragma unroll
-                for (int kk = 0; kk < KT; ++kk) U += uint64_t(wm[kk]) * uint64_t(win[o + tp[kk]] - win[o + tm[kk]]);
-                word = exact_round_div_u(U, p.G2, p.G2half, p.invG2, p.qsh);
+                for (int kk = 0; kk < KT; ++kk) N += uint64_t(wm[kk]) * uint64_t(win[o + tp[kk]] - win[o + tm[kk]]);
+                word = round_quotient(N, p.G2, p.invG2, p.qsh);
             } else {
                 float s = offo[t] * dc;
 #pragma unroll
