@@ -50,6 +50,12 @@
 namespace rsg {
 namespace dev {
 
+// Cache policy of the output stores: non-temporal.  The output is written
+// once and never read back by the kernel; streaming it past the caches keeps
+// the input's halo rows and shared span columns resident in L2 (measured at
+// 4096^2 FP32: 45.5 -> 38.8 us; non-temporal loads instead cost 30 %).
+constexpr int kStoreNT = 2;
+
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 typedef uint32_t v3u __attribute__((ext_vector_type(3)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
@@ -263,18 +269,18 @@ __device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, int voff, i
 template <>
 __device__ __forceinline__ void store_out<TrF32>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, voff, soff, kStoreNT);
 }
 template <>
 __device__ __forceinline__ void store_out<TrF16>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), rs, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), rs, voff, soff, kStoreNT);
 }
 template <>
 __device__ __forceinline__ void store_out<TrBF16>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
 {
     const uint32_t u = __float_as_uint(v);                          // finite v
-    __builtin_amdgcn_raw_buffer_store_b16(uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16), rs, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16), rs, voff, soff, kStoreNT);
 }
 
 // NC consecutive output samples of one lane at byte offset vo: one vector
@@ -287,38 +293,38 @@ __device__ __forceinline__ void store_group(__amdgpu_buffer_rsrc_t rs, int vo, c
 {
     constexpr int es = Tr::kSize;
     if constexpr (NC == 1) {
-        if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, vo, 0, 0);
-        else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0]), rs, vo, 0, 0);
-        else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[0]), rs, vo, 0, 0);
+        if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, vo, 0, kStoreNT);
+        else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0]), rs, vo, 0, kStoreNT);
+        else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[0]), rs, vo, 0, kStoreNT);
         return;
     } else {
         if (full && (es == 4 || vec)) {
             if constexpr (es == 4) {
                 if constexpr (NC == 2) {
-                    __builtin_amdgcn_raw_buffer_store_b64((v2u){w[0], w[1]}, rs, vo, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b64((v2u){w[0], w[1]}, rs, vo, 0, kStoreNT);
                 } else if constexpr (NC == 3) {
-                    __builtin_amdgcn_raw_buffer_store_b96((v3u){w[0], w[1], w[2]}, rs, vo, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b96((v3u){w[0], w[1], w[2]}, rs, vo, 0, kStoreNT);
                 } else {
-                    __builtin_amdgcn_raw_buffer_store_b128((v4u){w[0], w[1], w[2], w[3]}, rs, vo, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b128((v4u){w[0], w[1], w[2], w[3]}, rs, vo, 0, kStoreNT);
                 }
             } else if constexpr (es == 2 && NC == 2) {
-                __builtin_amdgcn_raw_buffer_store_b32(w[0] | (w[1] << 16), rs, vo, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(w[0] | (w[1] << 16), rs, vo, 0, kStoreNT);
             } else if constexpr (es == 1 && NC == 2) {
-                __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0] | (w[1] << 8)), rs, vo, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0] | (w[1] << 8)), rs, vo, 0, kStoreNT);
             } else {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, vo + 2 * c, 0, 0);
-                    else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, vo + c, 0, 0);
+                    if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, vo + 2 * c, 0, kStoreNT);
+                    else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, vo + c, 0, kStoreNT);
                 }
             }
         } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int o = (c < nlive) ? vo + c * es : kDropOffset;
-                if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[c], rs, o, 0, 0);
-                else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, o, 0, 0);
-                else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, o, 0, 0);
+                if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[c], rs, o, 0, kStoreNT);
+                else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, o, 0, kStoreNT);
+                else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, o, 0, kStoreNT);
             }
         }
     }
@@ -485,7 +491,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < G; ++j) {         // distinct offsets: not merged by the compiler
-            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (b * G + j), 0, 0);
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (b * G + j), 0, kStoreNT);
             else store_out<Tr>(rs_dst, kDropOffset - 64 * (b * G + j), 0, 0.0f);
         }
     }
@@ -626,7 +632,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
                 uint64_t N = ip.G2half;
 #pragma unroll
                 for (int k = 0; k < KT; ++k) N += uint64_t(wm[k]) * uint64_t(rv[j][2 * k] - rv[j][2 * k + 1]);
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(round_quotient(N, ip)), rs_dst, voff, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(round_quotient(N, ip)), rs_dst, voff, 0, kStoreNT);
             } else {
                 float o = c2dc;
 #pragma unroll
@@ -639,7 +645,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, 0);
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, kStoreNT);
             else store_out<Tr>(rs_dst, kDropOffset - 64 * (base + j), 0, 0.0f);
         }
     };
@@ -733,7 +739,8 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 // offsets, so every step issues the same memory operations and the waits
 // for the prefetched loads stay exact.
 // --------------------------------------------------------------------------
-template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE, int NC = 1, int NW_ = kCoWaves, int RB_ = kCoRows>
+template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE, int NC = 1, bool ZX = false, int NW_ = kCoWaves,
+          int RB_ = kCoRows>
 __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
 {
     using Acc = typename Tr::Acc;
@@ -896,7 +903,8 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     // of its samples inside the image: dcx (along x, per lane) and dcy
     // (along y, per output row) replace the DC gain near the borders, so
     // outside samples still enter every sum as exact zeros.
-    const bool zext = !kInt && boundary == RSG_ZERO;
+    constexpr bool zext = ZX;                  // float samples under zero extension
+    static_assert(!ZX || !kInt, "integer sums take no offsets");
     float cf[NC], cdc[NC], dcx[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -942,7 +950,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
-            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, 0);
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, kStoreNT);
             else store_out<Tr>(rs_dst, kDropOffset - 64 * (base + j), 0, 0.0f);
         }
     };
@@ -1185,7 +1193,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
                     }
                     combine_store(rv, i);
                 } else {
-                    if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * i, 0, 0);
+                    if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * i, 0, kStoreNT);
                     else store_out<Tr>(rs_dst, kDropOffset - 64 * i, 0, 0.0f);
                 }
             }
@@ -1230,6 +1238,15 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
     const int WC = ip.W * C;
     const bool interior = ip.vec && tg.a0 >= 0 && tg.a0 + SEG * NPL <= WC;
     if constexpr (CO) {
+        // float images under zero extension take the masked offsets (an
+        // instantiation of their own, so other images pay nothing for them)
+        if constexpr (!Tr::kInt) {
+            if (ip.boundary == RSG_ZERO) {
+                if (interior) stream_task_co<Tr, C, SEG, NPL, KT, false, NC, true>(ip, tg, lds);
+                else stream_task_co<Tr, C, SEG, NPL, KT, true, NC, true>(ip, tg, lds);
+                return;
+            }
+        }
         if (interior) stream_task_co<Tr, C, SEG, NPL, KT, false, NC>(ip, tg, lds);
         else stream_task_co<Tr, C, SEG, NPL, KT, true, NC>(ip, tg, lds);
     } else {

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_zpass(ZParams p)
                         o = fmaf(wf[k], ring[a * kWave + lane] - ring[b * kWave + lane], o);
                     }
                     const int z = tb + i - R;
-                    if (live) p.dst[int64_t(z) * p.plane + s] = o;
+                    if (live) __builtin_nontemporal_store(o, p.dst + int64_t(z) * p.plane + s);   // output: not read back
                 }
             }
         }
