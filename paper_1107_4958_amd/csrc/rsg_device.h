@@ -50,11 +50,16 @@
 namespace rsg {
 namespace dev {
 
-// Cache policy of the output stores: non-temporal.  The output is written
-// once and never read back by the kernel; streaming it past the caches keeps
-// the input's halo rows and shared span columns resident in L2 (measured at
-// 4096^2 FP32: 45.5 -> 38.8 us; non-temporal loads instead cost 30 %).
+// Cache policy of the output stores.  The output is written once and never
+// read back by the kernel: where a wave's store of a row covers whole 128-byte
+// lines (two or more bytes per lane), it streams past the caches
+// (non-temporal), which keeps the input's halo rows and shared span columns
+// resident in L2 (4096^2 FP32: 45.8 -> 43.6 us; non-temporal loads instead
+// cost 30 %).  Byte-per-lane stores (uint8, one column per lane) stay cached,
+// so that the L2 merges their 64-byte pieces before they reach memory
+// (non-temporal, they wrote 1.4 x the output bytes).
 constexpr int kStoreNT = 2;
+template <int BYTES_PER_LANE> constexpr int kStorePolicy = (BYTES_PER_LANE >= 2) ? kStoreNT : 0;
 
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 typedef uint32_t v3u __attribute__((ext_vector_type(3)));
@@ -269,18 +274,18 @@ __device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, int voff, i
 template <>
 __device__ __forceinline__ void store_out<TrF32>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, voff, soff, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, voff, soff, kStorePolicy<4>);
 }
 template <>
 __device__ __forceinline__ void store_out<TrF16>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), rs, voff, soff, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), rs, voff, soff, kStorePolicy<2>);
 }
 template <>
 __device__ __forceinline__ void store_out<TrBF16>(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float v)
 {
     const uint32_t u = __float_as_uint(v);                          // finite v
-    __builtin_amdgcn_raw_buffer_store_b16(uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16), rs, voff, soff, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b16(uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16), rs, voff, soff, kStorePolicy<2>);
 }
 
 // NC consecutive output samples of one lane at byte offset vo: one vector
@@ -292,39 +297,41 @@ __device__ __forceinline__ void store_group(__amdgpu_buffer_rsrc_t rs, int vo, c
                                             int nlive, bool vec)
 {
     constexpr int es = Tr::kSize;
+    constexpr int pol = kStorePolicy<es * NC>;
     if constexpr (NC == 1) {
-        if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, vo, 0, kStoreNT);
-        else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0]), rs, vo, 0, kStoreNT);
-        else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[0]), rs, vo, 0, kStoreNT);
+        if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, vo, 0, pol);
+        else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0]), rs, vo, 0, pol);
+        else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[0]), rs, vo, 0, pol);
         return;
     } else {
         if (full && (es == 4 || vec)) {
             if constexpr (es == 4) {
                 if constexpr (NC == 2) {
-                    __builtin_amdgcn_raw_buffer_store_b64((v2u){w[0], w[1]}, rs, vo, 0, kStoreNT);
+                    __builtin_amdgcn_raw_buffer_store_b64((v2u){w[0], w[1]}, rs, vo, 0, pol);
                 } else if constexpr (NC == 3) {
-                    __builtin_amdgcn_raw_buffer_store_b96((v3u){w[0], w[1], w[2]}, rs, vo, 0, kStoreNT);
+                    __builtin_amdgcn_raw_buffer_store_b96((v3u){w[0], w[1], w[2]}, rs, vo, 0, pol);
                 } else {
-                    __builtin_amdgcn_raw_buffer_store_b128((v4u){w[0], w[1], w[2], w[3]}, rs, vo, 0, kStoreNT);
+                    __builtin_amdgcn_raw_buffer_store_b128((v4u){w[0], w[1], w[2], w[3]}, rs, vo, 0, pol);
                 }
             } else if constexpr (es == 2 && NC == 2) {
-                __builtin_amdgcn_raw_buffer_store_b32(w[0] | (w[1] << 16), rs, vo, 0, kStoreNT);
+                __builtin_amdgcn_raw_buffer_store_b32(w[0] | (w[1] << 16), rs, vo, 0, pol);
             } else if constexpr (es == 1 && NC == 2) {
-                __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0] | (w[1] << 8)), rs, vo, 0, kStoreNT);
+                __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[0] | (w[1] << 8)), rs, vo, 0, pol);
             } else {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, vo + 2 * c, 0, kStoreNT);
-                    else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, vo + c, 0, kStoreNT);
+                    // strided element stores: partial lines, left to the L2 to merge
+                    if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, vo + 2 * c, 0, 0);
+                    else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, vo + c, 0, 0);
                 }
             }
         } else {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int o = (c < nlive) ? vo + c * es : kDropOffset;
-                if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[c], rs, o, 0, kStoreNT);
-                else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, o, 0, kStoreNT);
-                else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, o, 0, kStoreNT);
+                if constexpr (es == 4) __builtin_amdgcn_raw_buffer_store_b32(w[c], rs, o, 0, 0);
+                else if constexpr (es == 2) __builtin_amdgcn_raw_buffer_store_b16(uint16_t(w[c]), rs, o, 0, 0);
+                else __builtin_amdgcn_raw_buffer_store_b8(uint8_t(w[c]), rs, o, 0, 0);
             }
         }
     }
@@ -491,7 +498,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < G; ++j) {         // distinct offsets: not merged by the compiler
-            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (b * G + j), 0, kStoreNT);
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (b * G + j), 0, kStorePolicy<1>);
             else store_out<Tr>(rs_dst, kDropOffset - 64 * (b * G + j), 0, 0.0f);
         }
     }
@@ -632,7 +639,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
                 uint64_t N = ip.G2half;
 #pragma unroll
                 for (int k = 0; k < KT; ++k) N += uint64_t(wm[k]) * uint64_t(rv[j][2 * k] - rv[j][2 * k + 1]);
-                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(round_quotient(N, ip)), rs_dst, voff, 0, kStoreNT);
+                __builtin_amdgcn_raw_buffer_store_b8(uint8_t(round_quotient(N, ip)), rs_dst, voff, 0, kStorePolicy<1>);
             } else {
                 float o = c2dc;
 #pragma unroll
@@ -645,7 +652,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
     auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, kStoreNT);
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, kStorePolicy<1>);
             else store_out<Tr>(rs_dst, kDropOffset - 64 * (base + j), 0, 0.0f);
         }
     };
@@ -950,7 +957,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
-            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, kStoreNT);
+            if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, kStorePolicy<1>);
             else store_out<Tr>(rs_dst, kDropOffset - 64 * (base + j), 0, 0.0f);
         }
     };
@@ -1193,7 +1200,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
                     }
                     combine_store(rv, i);
                 } else {
-                    if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * i, 0, kStoreNT);
+                    if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * i, 0, kStorePolicy<1>);
                     else store_out<Tr>(rs_dst, kDropOffset - 64 * i, 0, 0.0f);
                 }
             }

@@ -127,7 +127,6 @@ struct PassParams {
     int32_t win_pitch;             // LDS words per wave window
     int32_t win_shift;             // window start offset (aligns its new part to 16 bytes)
     int32_t ostep;                 // store every ostep-th pixel of a row (1: all), compacted
-    int32_t final;                 // the pass writes the output image (stored non-temporally)
 };
 
 // One unit of work of a batched launch.

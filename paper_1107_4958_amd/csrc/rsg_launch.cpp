@@ -37,7 +37,6 @@ PassParams pass_params(const ImgParams& ip, int pass, void* mid)
     const int WoC = (ip.W + step - 1) / step * ip.C;   // intermediate rows: kept pixels x channels
     const int npl = ip.pnpl[pass];
     pp.ostep = step;
-    pp.final = (pass == 1);
     if (pass == 0) {                       // image rows -> intermediate (W*C) x H
         pp.src = ip.src;
         pp.dst = mid;

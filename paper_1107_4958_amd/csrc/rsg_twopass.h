@@ -57,25 +57,15 @@ struct TrU32 {
 
 template <int OUT> struct OutSize { static constexpr int v = (OUT == kOutU8) ? 1 : (OUT >= kOutF16 ? 2 : 4); };
 
-// Stores one staged 32-bit word as the output element; the final image
-// (`nt`) non-temporally, since nothing reads it back, the intermediate
-// normally, since the next pass reads it.
+// Stores one staged 32-bit word as the output element.  (Through the
+// caches: a wave writes 16 consecutive elements of a row, partial lines that
+// the L2 combines before they reach memory.)
 template <int OUT>
-__device__ __forceinline__ void store_pass_out(void* dst, int64_t idx, uint32_t w, bool nt)
+__device__ __forceinline__ void store_pass_out(void* dst, int64_t idx, uint32_t w)
 {
-    if constexpr (OUT == kOutU8) {
-        uint8_t* p = static_cast<uint8_t*>(dst) + idx;
-        if (nt) __builtin_nontemporal_store(uint8_t(w), p);
-        else *p = uint8_t(w);
-    } else if constexpr (OUT == kOutF16 || OUT == kOutBF16) {
-        uint16_t* p = static_cast<uint16_t*>(dst) + idx;
-        if (nt) __builtin_nontemporal_store(uint16_t(w), p);
-        else *p = uint16_t(w);
-    } else {
-        uint32_t* p = static_cast<uint32_t*>(dst) + idx;
-        if (nt) __builtin_nontemporal_store(w, p);
-        else *p = w;
-    }
+    if constexpr (OUT == kOutU8) static_cast<uint8_t*>(dst)[idx] = uint8_t(w);
+    else if constexpr (OUT == kOutF16 || OUT == kOutBF16) static_cast<uint16_t*>(dst)[idx] = uint16_t(w);
+    else static_cast<uint32_t*>(dst)[idx] = w;
 }
 
 // Boundary-extended position inside a row of `len` samples whose channels
@@ -297,7 +287,7 @@ __device__ __forceinline__ void pass_rows(const PassParams& p, int block, uint32
                     if (px - q * ostep) continue;
                     xo = q * C + (x - px * C);
                 }
-                store_pass_out<OUT>(p.dst, int64_t(xo) * p.dst_stride + row0 + w, stg[o * SP + w], p.final != 0);
+                store_pass_out<OUT>(p.dst, int64_t(xo) * p.dst_stride + row0 + w, stg[o * SP + w]);
             }
         }
         // with two staging tiles the next chunk writes the other one; the
