@@ -147,3 +147,21 @@ def test_plan_does_not_depend_on_the_boundary():
             d.b = b
             shapes.append(rsg.rsg_plan_shape(d))
         assert shapes[0] == shapes[1] == shapes[2], (H, W, C, shapes)
+
+
+def test_table_strip_width_field():
+    """A table line's optional last field selects the strip width: 2 the wide
+    form (128-sample strips at C = 1, 64-pixel strips at C = 3), 1 or no
+    field one column per lane; the override wins over the table."""
+    R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
+    _run_planner_code(
+        "hs, tasks, _ = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))\n"
+        "assert hs == 256 and tasks == 32 * 16, (hs, tasks)\n"
+        "rsg.rsg_tune_columns(1)\n"
+        "hs, tasks, _ = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))\n"
+        "assert tasks == 64 * 16, tasks\n",
+        "1 1 %d %d 0 %d 256 2\n" % (R, R, 1 << 40))
+    _run_planner_code(
+        "hs, tasks, _ = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))\n"
+        "assert hs == 256 and tasks == 64 * 16, (hs, tasks)\n",
+        "1 1 %d %d 0 %d 256\n1 1 0 1000 0 %d 128 1\n" % (R, R, 1 << 40, 1 << 40))
