@@ -51,6 +51,7 @@ def _torch_dtype(torch, dt):
 
 
 WIDE_C = (1, 3)                    # channel counts with a wide column form
+WIDE_MARGIN = 0.05                 # the wide form must beat the best other shape by this fraction
 
 
 def _time_config(rsg, torch, dt, side, C, sigma, K, reps):
@@ -156,6 +157,13 @@ def main(argv=None):
                     default = [v for k, v in res.items() if k == DEFAULT]
                     tuned = {k: v for k, v in res.items() if k != DEFAULT}
                     best = min(tuned, key=tuned.get)
+                    narrow = {k: v for k, v in tuned.items() if k[1] != 2}
+                    if best[1] == 2 and narrow:
+                        # the wide form only where it clearly wins: a batch
+                        # whose images mix widths runs one launch per width
+                        alt = min(narrow, key=narrow.get)
+                        if narrow[alt] <= tuned[best] * (1.0 + WIDE_MARGIN):
+                            best = alt
                     n = -(-side * C // 64) * side
                     rows.append(dict(dt=dt, C=C, R=R, n=n, hs=best[0], nc=best[1], us=tuned[best],
                                      default_us=default[0] if default else float("nan"),

@@ -718,12 +718,13 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 // --------------------------------------------------------------------------
 // Cooperative form of the streaming loop: one task per workgroup of
 // kCoWaves waves that share the strip.  Step m covers iterations
-// [m MB, (m + 1) MB), MB = kCoWaves * kCoRows; wave w takes the block of
-// kCoRows iterations starting at m MB + w kCoRows and runs both passes on it:
+// [m MB, (m + 1) MB), MB = kCoWaves * RB (RB = co_rows(NC): 8 rows, 4 for
+// the wide column form); wave w takes the block of RB iterations starting at
+// m MB + w RB and runs both passes on it:
 //
-//   row pass    its groups of G rows (loads prefetched two groups ahead in
+//   row pass    its groups of G rows (loads prefetched one step ahead in
 //               the wave's own sequence, running sums, row tile, Eq. indep
-//               along x) -> T of its kCoRows rows in registers;
+//               along x) -> T of its RB rows in registers;
 //   column sums the block's running sums of T (Eq. alg1 down the column,
 //               in registers), its total to LDS; barrier; the block's carry
 //               (sum of the earlier blocks' totals, added in the same order
@@ -732,14 +733,15 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 //   column out  K box differences down the column (Eq. indep) for the
 //               block's rows, read from the ring, and one store per row.
 //
-// The ring holds L >= MB + 2R + 1 rows (a multiple of kCoRows) plus kCoRows
+// The ring holds L >= MB + 2R + 1 rows (a multiple of RB) plus RB
 // mirror rows, so the taps of a block are read at (per-block slot) + row
 // without a modulo.  Two barriers per step of MB rows, all waves doing the
 // same work, several steps of loads in flight: the strip streams without a
 // serial chain of LDS round trips per row.  Float columns sum T - c with c a
 // per-column constant (the input sample at the task's first row), restored
 // through the DC gain of the boxes, so the sums stay at the size of local
-// variations (c = 0 under zero extension).
+// variations (under zero extension only samples inside the image are
+// offset, and each box takes back the share of its inside samples).
 //
 // Iteration `it` reads input row ybase + it and, for it >= 2R + 1, emits
 // output row ybase + it - R.  Rows past the task are stored to dropped
@@ -747,7 +749,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 // for the prefetched loads stay exact.
 // --------------------------------------------------------------------------
 template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE, int NC = 1, bool ZX = false, int NW_ = kCoWaves,
-          int RB_ = kCoRows>
+          int RB_ = co_rows(NC)>
 __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
 {
     using Acc = typename Tr::Acc;
@@ -760,7 +762,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     constexpr int RB = RB_;                    // rows per wave per step
     constexpr int NGW = RB / G;                // row groups per wave per step
     constexpr int MB = NW * RB;                // rows per step
-    constexpr int PF = 2;                      // groups of loads in flight per wave
+    constexpr int PF = (NGW >= 2) ? 2 : 1;     // groups of loads in flight per wave (one step ahead)
     static_assert(RB % G == 0 && NGW % PF == 0, "a step holds whole groups and whole prefetch rounds");
     static_assert(PW <= PP, "tile pitch");
     constexpr int es = Tr::kSize;

@@ -260,7 +260,6 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     const int nc_ov = g_nc_override.load(std::memory_order_relaxed);
     const int nc_want = nc_ov > 0 ? nc_ov : (nc_t > 0 ? nc_t : 1);
     const int nc_first = (co && step == 1 && nc_want > 1) ? wide_nc(C) : 1;
-    const int Lco = (kCoStep + 2 * R + 1 + kCoRows - 1) / kCoRows * kCoRows;
     for (int nci = nc_first; nci >= 1 && !seg; nci = (nci > 1) ? 1 : 0) {
         int64_t cols = int64_t(kWave) * nci;
         if (step > 1) {
@@ -276,7 +275,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
             const int al = lcm_i(C, std::max(1, unit / es));
             const int64_t span = cols + int64_t(2 * R + 1) * C + al - 1;
             if (span > int64_t(sg) * n) continue;
-            if (nci > 1 && tile_lds_bytes_co(sg, n, Lco, nci) + 4u * kBatchSlotWords > kLdsLimit) break;
+            if (nci > 1 && tile_lds_bytes_co(sg, n, co_ring_rows(R, nci), nci) + 4u * kBatchSlotWords > kLdsLimit) break;
             seg = sg; npl = n; align = al; nc = nci;
         }
     }
@@ -312,7 +311,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     }
     p.G = kWave / seg;
     p.L = (2 * R + 1 + p.G + p.G - 1) / p.G * p.G;
-    p.Lco = Lco;
+    p.Lco = co_ring_rows(R, nc);
     p.co = co;
     p.nc = nc;
     {   // vector stores of a lane's columns: 2-byte and 1-byte elements need
