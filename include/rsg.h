@@ -299,9 +299,10 @@ int rsg_server_destroy(rsg_server* s);
  * windows) and the LDS is the larger pass's.  Host-only: d->src and d->dst
  * are compared but never dereferenced.  Segment heights come from the tuning
  * table named by the environment variable RSG_TUNE_TABLE (read once, lines
- * "dtype C rlo rhi nlo nhi hs [nc]", with R the largest box half-width, n
- * the number of 64-sample strips times H and nc the columns per lane of
- * rsg_tune_columns), else from a built-in rule.  This is
+ * "dtype C rlo rhi nlo nhi hs [nc [lo]]", with R the largest box
+ * half-width, n the number of 64-sample strips times H, nc the columns per
+ * lane of rsg_tune_columns and lo the first layout of rsg_tune_layout),
+ * else from a built-in rule.  This is
  * the image's own plan; in a batch, uint8 images may get longer segments
  * (same results).  Any output pointer may be NULL.
  * Errors: as rsg_gauss_filter. */
@@ -342,6 +343,16 @@ int rsg_tune_path(int32_t path);
  * not fit.  Results agree to FP32 rounding (bit-identical for uint8).  For
  * the autotuner and tests.  Errors: RSG_EINVAL (negative). */
 int rsg_tune_columns(int32_t columns);
+
+/* Process-wide first row-scan layout of the fused kernel for every later
+ * plan: 0 lets the planner choose (the tuning table's optional last field,
+ * else the first layout whose rows cover the task's span), 1..3 start the
+ * search at that layout.  Layouts are (lanes per row, samples per lane)
+ * = (16, 8), (32, 8), (64, 8), (64, 16) at C = 1, 2, 4 and (16, 12), (32, 12),
+ * (64, 12), (64, 24) at C = 3: later ones scan fewer, wider rows per group.
+ * Results agree to FP32 rounding (bit-identical for
+ * uint8).  For the autotuner and tests.  Errors: RSG_EINVAL (not in 0..3). */
+int rsg_tune_layout(int32_t first);
 
 /* ---------------------------------------------------------------------- */
 /* Measurement.                                                            */

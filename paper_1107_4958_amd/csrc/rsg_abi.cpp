@@ -120,6 +120,14 @@ int rsg_tune_columns(int32_t columns)
     return RSG_OK;
 }
 
+int rsg_tune_layout(int32_t first)
+{
+    using namespace rsg;
+    if (first < 0 || first >= kLayouts) return set_error(RSG_EINVAL, "layout must be in 0..%d", kLayouts - 1);
+    set_layout_override(first);
+    return RSG_OK;
+}
+
 int rsg_tune_override(int32_t seg_height)
 {
     using namespace rsg;

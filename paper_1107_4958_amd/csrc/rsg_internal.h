@@ -152,6 +152,8 @@ void set_path_override(int path);
 // Process-wide columns-per-lane override of the cooperative form (0: none,
 // 1: one, > 1: wide_nc(C)).
 void set_nc_override(int nc);
+// Process-wide first row-scan layout the planner tries (0: the first that fits).
+void set_layout_override(int lo);
 
 // Launchers (rsg_kernels.hip).
 int launch_single(const ImgParams& ip, hipStream_t stream);

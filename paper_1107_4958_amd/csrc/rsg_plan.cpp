@@ -34,19 +34,22 @@ constexpr uint32_t kLdsLimit = 160u * 1024u;    // gfx950: 160 KiB of LDS per CU
 int gcd_i(int a, int b) { while (b) { int t = a % b; a = b; b = t; } return a; }
 int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
 
-// Tuning table (text): lines "dtype C rlo rhi nlo nhi hs [nc]", '#' starts
-// a comment.  An image of dtype and channel count C whose largest half-width
-// R lies in [rlo, rhi] and whose work size n = strips * H (strips of 64
-// samples) lies in [nlo, nhi] takes the fused kernel with segment height hs
-// from the first matching line, or the two-pass path if hs is -1; nc > 1
-// selects the wide column form (wide_nc(C) columns per lane), 1 one column
-// per lane, 0 or none the built-in rule.
-struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs, nc; };
+// Tuning table (text): lines "dtype C rlo rhi nlo nhi hs [nc [lo]]", '#'
+// starts a comment.  An image of dtype and channel count C whose largest
+// half-width R lies in [rlo, rhi] and whose work size n = strips * H (strips
+// of 64 samples) lies in [nlo, nhi] takes the fused kernel with segment
+// height hs from the first matching line, or the two-pass path if hs is -1;
+// nc > 1 selects the wide column form (wide_nc(C) columns per lane), 1 one
+// column per lane, 0 or none the built-in rule; lo > 0 starts the search for
+// a row-scan layout at layout lo (wider rows per group, fewer rows), 0 or
+// none at the first.
+struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs, nc, lo; };
 std::once_flag g_tune_once;
 std::vector<TuneEntry> g_tune;
 std::atomic<int> g_hs_override{0};
 std::atomic<int> g_path_override{0};
 std::atomic<int> g_nc_override{0};
+std::atomic<int> g_lo_override{0};
 
 // Two-pass geometry: the smallest chunk (64 NPL samples) that holds the
 // window head (2R + 1) C and fits the LDS with one staging tile (0 if none
@@ -84,12 +87,13 @@ void load_tune_table()
         TuneEntry e;
         if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.nlo >> e.nhi >> e.hs && (e.hs > 0 || e.hs == -1)) {
             if (!(is >> e.nc) || e.nc < 0) e.nc = 0;
+            if (!(is >> e.lo) || e.lo < 0 || e.lo >= kLayouts) e.lo = 0;
             g_tune.push_back(e);
         }
     }
 }
 
-bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs, int* nc)
+bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs, int* nc, int* lo)
 {
     const int ov = g_hs_override.load(std::memory_order_relaxed);
     if (ov > 0) { *hs = ov; return true; }
@@ -98,6 +102,7 @@ bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs, int* nc)
         if (e.dtype == dtype && e.C == C && R >= e.rlo && R <= e.rhi && n >= e.nlo && n <= e.nhi) {
             *hs = e.hs;
             *nc = e.nc;
+            *lo = e.lo;
             return true;
         }
     return false;
@@ -147,6 +152,7 @@ int check_boxes(const rsg_boxes& b, bool need_u8)
 void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_order_relaxed); }
 void set_path_override(int path) { g_path_override.store(path, std::memory_order_relaxed); }
 void set_nc_override(int nc) { g_nc_override.store(nc > 0 ? nc : 0, std::memory_order_relaxed); }
+void set_layout_override(int lo) { g_lo_override.store(lo > 0 ? lo : 0, std::memory_order_relaxed); }
 
 int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
 {
@@ -235,8 +241,10 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1, p.pst[1], p.ptr[1]);
     }
     const int ov = g_path_override.load(std::memory_order_relaxed);
-    int hs_t = 0, nc_t = 0;
-    const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t, &nc_t);
+    int hs_t = 0, nc_t = 0, lo_t = 0;
+    const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t, &nc_t, &lo_t);
+    const int lo_ov = g_lo_override.load(std::memory_order_relaxed);
+    const int lo_first = lo_ov > 0 ? lo_ov : lo_t;      // first row-scan layout tried
     bool two = two_ok && (tabled ? hs_t < 0 : R * C >= kTwoPassMinRC);
     if (ov == 1 || ov == 3) two = false;
     // strided output: the fused two-wave form (which stores every step-th row
@@ -267,7 +275,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
             for (int k = 0; k < C; ++k) np = std::max<int64_t>(np, ((kWave * k) % C + kWave - 1) / C + 1);
             cols = ((np - 1) * step + 1) * C;
         }
-        for (int i = 0; i < kLayouts && !seg; ++i) {
+        for (int i = lo_first; i < kLayouts && !seg; ++i) {
             int sg, n;
             scan_layout(C, i, &sg, &n);
             const int cb = n * es;                   // chunk bytes

@@ -404,3 +404,20 @@ def test_full_image_4096(dtype, sigma):
     times (Section 3.4 composes the passes over every pixel)."""
     img = synthimg.image(4096, 4096, 1, dtype, seed=2)
     _check(img, dtype, sigma, 3, oracle.REPLICATE)
+
+
+@pytest.mark.parametrize("layout", [1, 2, 3])
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+@pytest.mark.parametrize("H,W,C,sigma,K,boundary", [(97, 250, 1, 2.0, 3, oracle.REPLICATE),
+                                                     (61, 211, 3, 1.0, 4, oracle.ZERO),
+                                                     (130, 300, 2, 3.0, 5, oracle.REFLECT)])
+def test_forced_row_layouts(layout, dtype, H, W, C, sigma, K, boundary):
+    """Narrow boxes on the wider row-scan layouts the tuner may choose
+    (rsg_tune_layout): tiles much wider than the span a task needs."""
+    import paper_1107_4958_amd as rsg
+    img = synthimg.image(H, W, C, dtype, seed=H + 3 * layout)
+    rsg.rsg_tune_layout(layout)
+    try:
+        _check(img, dtype, sigma, K, boundary)
+    finally:
+        rsg.rsg_tune_layout(0)

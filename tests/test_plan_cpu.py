@@ -165,3 +165,25 @@ def test_table_strip_width_field():
         "hs, tasks, _ = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))\n"
         "assert hs == 256 and tasks == 64 * 16, (hs, tasks)\n",
         "1 1 %d %d 0 %d 256\n1 1 0 1000 0 %d 128 1\n" % (R, R, 1 << 40, 1 << 40))
+
+
+def test_table_first_layout_field():
+    """The table's layout field (and rsg_tune_layout) starts the planner's
+    search at a wider row-scan layout: same strips and segments, another
+    row tile (fewer, wider rows per group); out-of-range values are refused."""
+    R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
+    _run_planner_code(
+        "hs, tasks, lds = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))\n"
+        "rsg.rsg_tune_layout(0)\n"
+        "hs0, tasks0, lds0 = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))\n"
+        "assert (hs, tasks) == (hs0, tasks0) == (256, 64 * 16) and lds == lds0, (hs, tasks, lds)\n"
+        "rsg.rsg_tune_layout(2)\n"
+        "hs2, tasks2, lds2 = rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))\n"
+        "assert (hs2, tasks2) == (256, 64 * 16) and lds2 != lds, (lds2, lds)\n"
+        "with pytest.raises(rsg.RsgError):\n    rsg.rsg_tune_layout(4)\n",
+        "1 1 %d %d 0 %d 256 1 0\n" % (R, R, 1 << 40))
+    a = _run_planner_code("print(rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))[2])\n",
+                          "1 1 %d %d 0 %d 256 1 1\n" % (R, R, 1 << 40))
+    b = _run_planner_code("print(rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))[2])\n",
+                          "1 1 %d %d 0 %d 256 1\n" % (R, R, 1 << 40))
+    assert int(a) != int(b)
