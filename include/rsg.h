@@ -331,17 +331,20 @@ int rsg_tune_override(int32_t seg_height);
  * RSG_EUNSUPPORTED when the forced path cannot hold the boxes. */
 int rsg_tune_path(int32_t path);
 
-/* Process-wide strip width of the fused kernel's workgroups for every later
- * unstrided plan: 0 lets the planner choose (the tuning table's optional
- * last field, else one column per lane), 1 gives each lane one sample
- * column (strips of 64 samples), any larger value the wide form: each lane
- * owns two adjacent columns at C = 1 (strips of 128 samples) and one
- * pixel's three channels at C = 3 (strips of 64 pixels); C = 2 and 4 keep
- * one column per lane.  The wide form shortens the row span each output
- * pays for and moves a lane's columns with one vector access, at the price
- * of a larger LDS ring; it falls back to one column where that ring would
- * not fit.  Results agree to FP32 rounding (bit-identical for uint8).  For
- * the autotuner and tests.  Errors: RSG_EINVAL (negative). */
+/* Process-wide task form of the fused kernel for every later unstrided
+ * plan: 0 lets the planner choose (the tuning table's optional field, else
+ * 1); 1 gives each lane one sample column (strips of 64 interleaved
+ * samples); 2 the wide form, where each lane owns two adjacent columns at
+ * C = 1 (strips of 128 samples) or one pixel's three channels at C = 3
+ * (strips of 64 pixels) and moves them with one vector access, at the price
+ * of a larger LDS ring (C = 2 and 4, and images whose ring would not fit,
+ * keep one column per lane); 3 channel-planar tasks on multi-channel images
+ * (C >= 2): each task filters 64 pixels of one channel with the one-channel
+ * kernel, reading its samples C apart, so its row span is 64 + 2R + 1
+ * pixels instead of 64 + (2R + 1) C interleaved samples for 64 / C pixels
+ * (volumes keep interleaved tasks).  Results agree to FP32 rounding
+ * (bit-identical for uint8).  For the autotuner and tests.
+ * Errors: RSG_EINVAL (not in 0..3). */
 int rsg_tune_columns(int32_t columns);
 
 /* Process-wide first row-scan layout of the fused kernel for every later

@@ -11,10 +11,11 @@ element type, the channel count, R and the amount of work (strips x rows),
 so the table is keyed on exactly those: lines "dtype C rlo rhi nlo nhi hs
 nc lo", with hs = -1 selecting the two-pass path (row filter into a
 transposed intermediate, twice), which wins for wide boxes.  nc is the strip
-width in lanes' columns (rsg_tune_columns): 1 for strips of 64 samples, 2
-for the wide form that C = 1 and C = 3 images have (lanes owning two columns
-or one pixel), which shortens the row span per output but needs a larger
-LDS ring.  lo is the first row-scan layout the planner tries
+form (rsg_tune_columns): 1 for strips of 64 interleaved samples, 2 for the
+wide form that C = 1 and C = 3 images have (lanes owning two columns or one
+pixel), which shortens the row span per output but needs a larger LDS ring,
+3 for channel-planar tasks of multi-channel images (one channel of 64
+pixels per task).  lo is the first row-scan layout the planner tries
 (rsg_tune_layout): 0 the narrowest whose rows cover the span, higher ones
 scan fewer, wider rows per group.
 
@@ -79,7 +80,7 @@ def _time_config(rsg, torch, dt, side, C, sigma, K, reps):
     # with segment height h, strip width nc and first layout lo;
     # (TWO_PASS, 0, 0): the two-pass path
     shapes = [(0, 0, 0)]
-    for nc in ((1, 2) if C in WIDE_C else (1,)):
+    for nc in (1,) + ((2,) if C in WIDE_C else ()) + ((3,) if C >= 2 else ()):
         for lo in range(LAYOUTS):
             shapes += [(h, nc, lo) for h in CANDIDATES if h <= side]
     shapes.append((TWO_PASS, 0, 0))
@@ -172,10 +173,11 @@ def main(argv=None):
                     default = [v for k, v in res.items() if k == DEFAULT]
                     tuned = {k: v for k, v in res.items() if k != DEFAULT}
                     best = min(tuned, key=tuned.get)
-                    narrow = {k: v for k, v in tuned.items() if k[1] != 2}
-                    if best[1] == 2 and narrow:
-                        # the wide form only where it clearly wins: a batch
-                        # whose images mix widths runs one launch per width
+                    narrow = {k: v for k, v in tuned.items() if k[1] not in (2, 3)}
+                    if best[1] in (2, 3) and narrow:
+                        # the wide and channel-planar forms only where they
+                        # clearly win: a batch whose images mix forms runs one
+                        # launch per form
                         alt = min(narrow, key=narrow.get)
                         if narrow[alt] <= tuned[best] * (1.0 + WIDE_MARGIN):
                             best = alt

@@ -52,7 +52,7 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
         int64_t fixed = 0, strips = 0;
         for (int i = 0; i < n; ++i) {
             if (imgs[i].path != kPathFused) continue;
-            if (imgs[i].dtype == RSG_U8) strips += imgs[i].nstrips;
+            if (imgs[i].dtype == RSG_U8) strips += int64_t(imgs[i].nstrips) * std::max(1, imgs[i].nslices);
             else fixed += imgs[i].ntasks;
         }
         if (strips > 0) {
@@ -115,7 +115,8 @@ int rsg_tune_path(int32_t path)
 int rsg_tune_columns(int32_t columns)
 {
     using namespace rsg;
-    if (columns < 0) return set_error(RSG_EINVAL, "columns per lane must be >= 0");
+    if (columns < 0 || columns > 3)
+        return set_error(RSG_EINVAL, "task form must be 0 (planner), 1 (one column), 2 (wide) or 3 (channel-planar)");
     set_nc_override(columns);
     return RSG_OK;
 }

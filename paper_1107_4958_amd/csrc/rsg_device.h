@@ -774,6 +774,9 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     const int W = ip.W;
     const int WC = W * C;
     const int boundary = ip.boundary;
+    // samples from one pixel to the next: 1, or the image's channel count
+    // for channel-planar tasks (C = 1 here; the slice offset selects the channel)
+    const int ps = ip.pstride > 1 ? ip.pstride : 1;
 
     // LDS: [row tiles NW x G x PP][block totals NW x RP][ring (L + RB) x RP]
     Acc* Pt = reinterpret_cast<Acc*>(lds) + wave * G * PP;
@@ -802,7 +805,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     // groups whose rows all lie in [y_lo, H) start at y_lo + [0, fast_n)
     const int fast_n = max(0, H - G - y_lo + 1);
     const char* sbase = reinterpret_cast<const char*>(ip.src) + tg.slice_off + int64_t(y_lo) * sstride;
-    const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(H - 1 - y_lo) * sstride + int64_t(WC) * es);
+    const __amdgpu_buffer_rsrc_t rs_src = make_rsrc(sbase, int64_t(H - 1 - y_lo) * sstride + int64_t(WC) * ps * es);
     const int cs = tg.a0 + NPL * q;
     const int vec_voff = cs * es;
     int eoff[EDGE ? NPL : 1];
@@ -812,7 +815,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
         for (int i = 0; i < NPL; ++i) {
             const int x = x0 + i / C;
             const int xe = ext_index(x, W, boundary);
-            eoff[i] = (xe >= 0) ? (xe * C + i % C) * es : -1;
+            eoff[i] = (xe >= 0) ? (xe * C + i % C) * ps * es : -1;
         }
     }
     const int sstride32 = int(sstride);
@@ -893,7 +896,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     // the kept rows oq0 .. oq1 - 1 of the output image; rows outside the
     // descriptor and samples past the row are stored to out-of-range offsets.
     int oq0 = tg.y0, nrows = tg.hs;
-    const uint32_t ocol = (oidx0 < orow_len) ? uint32_t(oidx0 * es) : kDropColumn;
+    const uint32_t ocol = (oidx0 < orow_len) ? uint32_t(oidx0 * ps * es) : kDropColumn;
     const bool lane_full = oidx0 + NC <= orow_len;
     const int nlive = orow_len - oidx0;
     const bool ovec = ip.ovec != 0;
@@ -903,7 +906,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
     }
     const char* dbase = reinterpret_cast<char*>(ip.dst) + tg.slice_off + int64_t(oq0) * dstride;
     const __amdgpu_buffer_rsrc_t rs_dst =
-        make_rsrc(dbase, nrows > 0 ? int64_t(nrows - 1) * dstride + int64_t(orow_len) * es : 0);
+        make_rsrc(dbase, nrows > 0 ? int64_t(nrows - 1) * dstride + int64_t(orow_len) * ps * es : 0);
     const uint32_t dstr = uint32_t(dstride);
     // Float offsets.  Each group of rows subtracts one of its samples (off)
     // and each column the input sample at the task's first row (cf); they
@@ -926,7 +929,7 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
         const int yc = zext ? min(max(tg.ybase, 0), H - 1) : ext_index(tg.ybase, H, boundary);   // >= y_lo
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            cf[c] = Tr_load_one<Tr>(rs_src, (yc - y_lo) * sstride32 + min(s + c, WC - 1) * es);
+            cf[c] = Tr_load_one<Tr>(rs_src, (yc - y_lo) * sstride32 + min(s + c, WC - 1) * ps * es);
         if (zext) {
             off_lane = min(SEG - 1, max(0, (NPL - 1 - tg.a0) / NPL));
 #pragma unroll

@@ -70,7 +70,8 @@ template <class Tr>
 int launch_single_t(const ImgParams& ip, hipStream_t st)
 {
     int rc;
-    switch (ip.C) {
+    // channel-planar tasks run the kernel of one channel
+    switch (ip.pstride > 1 ? 1 : ip.C) {
     case 1: rc = launch_layout<Tr, 1>(ip, st); break;
     case 2: rc = launch_layout<Tr, 2>(ip, st); break;
     case 3: rc = launch_layout<Tr, 3>(ip, st); break;

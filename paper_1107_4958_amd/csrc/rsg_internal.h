@@ -81,6 +81,7 @@ struct ImgParams {
     int32_t step;                  // output stride in pixels along both axes (1: every pixel; two-pass only)
     int32_t nslices;               // fused path: a stack of this many equal images (<= 1: one image)
     int64_t slice_stride;          // elements from one image of the stack to the next (source and destination)
+    int32_t pstride;               // samples from one pixel to the next in a task (> 1: channel-planar tasks)
     int32_t co;                    // fused path: 1 = cooperative workgroups of kCoWaves waves, 0 = one wave
     int32_t nc;                    // cooperative form: consecutive columns per lane (1, or wide_nc(C))
     int32_t ovec;                  // the destination allows one vector store per lane's columns
@@ -144,13 +145,13 @@ struct BatchTask {
 // Plan for one image: validates, fits (cached), picks the tile shape.
 // step > 1: strided output (two-pass path); hs_pref > 0: segment height of a
 // fused plan chosen by the caller (volumes), instead of the table or rule
-int plan_image(const rsg_image_desc& d, ImgParams* ip, int step = 1, int hs_pref = 0);
+int plan_image(const rsg_image_desc& d, ImgParams* ip, int step = 1, int hs_pref = 0, bool planar_ok = true);
 // Process-wide segment height that overrides the tuning table (0: none).
 void set_hs_override(int hs);
 // Process-wide path override (0: planner's choice, 1: fused, 2: two-pass).
 void set_path_override(int path);
 // Process-wide columns-per-lane override of the cooperative form (0: none,
-// 1: one, > 1: wide_nc(C)).
+// 1: one, 2: wide_nc(C), 3: channel-planar tasks for C >= 2).
 void set_nc_override(int nc);
 // Process-wide first row-scan layout the planner tries (0: the first that fits).
 void set_layout_override(int lo);

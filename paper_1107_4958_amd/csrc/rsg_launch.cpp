@@ -182,7 +182,8 @@ int launch_batch(const ImgParams* h_imgs, int nimg, const BatchTask* h_tasks, in
     std::map<std::tuple<int, int, int, int, int>, std::vector<BatchTask>> classes;
     for (int t = 0; t < ntasks; ++t) {
         const ImgParams& ip = h_imgs[h_tasks[t].img];
-        classes[std::make_tuple(ip.dtype, ip.C, ip.kt, ip.co, ip.co ? ip.nc : 1)].push_back(h_tasks[t]);
+        // channel-planar images run the one-channel kernel
+        classes[std::make_tuple(ip.dtype, ip.pstride > 1 ? 1 : ip.C, ip.kt, ip.co, ip.co ? ip.nc : 1)].push_back(h_tasks[t]);
     }
 
     // two-pass images: intermediates after the header, pass parameters 2j

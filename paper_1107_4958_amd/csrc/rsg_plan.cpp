@@ -154,7 +154,7 @@ void set_path_override(int path) { g_path_override.store(path, std::memory_order
 void set_nc_override(int nc) { g_nc_override.store(nc > 0 ? nc : 0, std::memory_order_relaxed); }
 void set_layout_override(int lo) { g_lo_override.store(lo > 0 ? lo : 0, std::memory_order_relaxed); }
 
-int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
+int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref, bool planar_ok)
 {
     if (step < 1) return set_error(RSG_EINVAL, "output step must be >= 1 (got %d)", step);
     if (!d.src || !d.dst) return set_error(RSG_EINVAL, "NULL image pointer");
@@ -264,12 +264,19 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     // (kCoWaves waves per task); path override 3 selects the one-wave form
     const int co = (ov == 3) ? 0 : 1;
     int seg = 0, npl = 0, align = 1, nc = 1;
-    // columns per lane: the override, else the table, else one
+    // columns per lane: the override, else the table, else one.  3 asks for
+    // channel-planar tasks: each task filters one channel of a multi-channel
+    // image (the kernel of one channel, pixels C samples apart), so its row
+    // span is 64 + 2R + 1 pixels of that channel instead of 64 + (2R + 1)C
+    // interleaved samples for 64 / C pixels
     const int nc_ov = g_nc_override.load(std::memory_order_relaxed);
     const int nc_want = nc_ov > 0 ? nc_ov : (nc_t > 0 ? nc_t : 1);
-    const int nc_first = (co && step == 1 && nc_want > 1) ? wide_nc(C) : 1;
+    const bool planar_possible = co && step == 1 && C >= 2 && planar_ok;
+    bool planar = planar_possible && nc_want == 3;
+    const int CK = planar ? 1 : C;                       // channels of the kernel
+    const int nc_first = (co && step == 1 && nc_want == 2) ? wide_nc(C) : 1;
     for (int nci = nc_first; nci >= 1 && !seg; nci = (nci > 1) ? 1 : 0) {
-        int64_t cols = int64_t(kWave) * nci;
+        int64_t cols = int64_t(kWave) * nci;            // samples (pixels when planar)
         if (step > 1) {
             int64_t np = 0;                          // pixels a strip of 64 kept samples spans
             for (int k = 0; k < C; ++k) np = std::max<int64_t>(np, ((kWave * k) % C + kWave - 1) / C + 1);
@@ -277,14 +284,26 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         }
         for (int i = lo_first; i < kLayouts && !seg; ++i) {
             int sg, n;
-            scan_layout(C, i, &sg, &n);
+            scan_layout(CK, i, &sg, &n);
             const int cb = n * es;                   // chunk bytes
             const int unit = gcd_i(cb, 16);          // vector load granule
-            const int al = lcm_i(C, std::max(1, unit / es));
-            const int64_t span = cols + int64_t(2 * R + 1) * C + al - 1;
+            const int al = lcm_i(CK, std::max(1, unit / es));
+            const int64_t span = cols + int64_t(2 * R + 1) * CK + al - 1;
             if (span > int64_t(sg) * n) continue;
             if (nci > 1 && tile_lds_bytes_co(sg, n, co_ring_rows(R, nci), nci) + 4u * kBatchSlotWords > kLdsLimit) break;
             seg = sg; npl = n; align = al; nc = nci;
+        }
+    }
+    if (!seg && !two && !planar && planar_possible && !(two_ok && ov != 1 && ov != 3)) {
+        // neither an interleaved span nor the two-pass window holds the
+        // boxes: one channel per task needs only 64 + 2R + 1 pixels
+        for (int i = lo_first; i < kLayouts && !seg; ++i) {
+            int sg, n;
+            scan_layout(1, i, &sg, &n);
+            const int al = std::max(1, gcd_i(n * es, 16) / es);
+            if (int64_t(kWave) + int64_t(2 * R + 1) + al - 1 > int64_t(sg) * n) continue;
+            seg = sg; npl = n; align = al; nc = 1;
+            planar = true;
         }
     }
     if (!seg && !two) {
@@ -312,11 +331,12 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     p.seg = seg;
     p.npl = npl;
     p.align = align;
-    {
+    {   // (channel-planar tasks read their channel element by element)
         const int unit = gcd_i(npl * es, 16);
         const uintptr_t sa = reinterpret_cast<uintptr_t>(d.src);
-        p.vec = (sa % unit == 0) && ((ss * es) % unit == 0);
+        p.vec = !planar && (sa % unit == 0) && ((ss * es) % unit == 0);
     }
+    p.pstride = planar ? C : 1;
     p.G = kWave / seg;
     p.L = (2 * R + 1 + p.G + p.G - 1) / p.G * p.G;
     p.Lco = co_ring_rows(R, nc);
@@ -335,11 +355,17 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
         if (need > kLdsLimit)
             return set_error(RSG_EUNSUPPORTED, "tile needs %u bytes of LDS (limit %u)", need, kLdsLimit);
     }
-    // a strip is 64 nc output samples (strided: 64 kept samples)
-    p.nstrips = int((WoC + int64_t(kWave) * nc - 1) / (int64_t(kWave) * nc));
+    // a strip is 64 nc output samples (strided: 64 kept samples; planar: 64
+    // pixels of one channel, the channels a stack of C slices one sample apart)
+    p.nstrips = int((WoC / (planar ? C : 1) + int64_t(kWave) * nc - 1) / (int64_t(kWave) * nc));
+    if (planar) {
+        p.nslices = C;
+        p.slice_stride = 1;
+    }
 
     // ---- segment height ----
-    int hs = hs_pref > 0 ? hs_pref : ((tabled && hs_t > 0) ? hs_t : default_hs(d.H, p.nstrips, R, p.lds_bytes));
+    int hs = hs_pref > 0 ? hs_pref
+                         : ((tabled && hs_t > 0) ? hs_t : default_hs(d.H, p.nstrips * std::max(1, p.nslices), R, p.lds_bytes));
     hs = std::max(1, std::min(hs, d.H));
     {   // every offset a task touches (rows ybase .. ybase + its padded
         // iteration count, times the larger stride) must stay below 2^30
@@ -361,7 +387,7 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref)
     p.step = step;
     p.hs = hs;
     p.nsegs = (d.H + hs - 1) / hs;
-    const int64_t nt = int64_t(p.nstrips) * p.nsegs;
+    const int64_t nt = int64_t(p.nstrips) * p.nsegs * std::max(1, p.nslices);
     if (nt > (int64_t(1) << 30)) return set_error(RSG_EUNSUPPORTED, "too many tasks");
     p.ntasks = int(nt);
     *ip = p;

@@ -60,7 +60,7 @@ extern "C" int rsg_gauss_filter_3d(const void* d_src, void* d_dst, int D, int H,
     const int hs_pref = int(std::max<int64_t>(16, (H + per_strip - 1) / per_strip));
     std::vector<ImgParams> imgs(1);
     std::vector<BatchTask> tasks;
-    int rc = plan_image(descs[0], &imgs[0], 1, hs_pref);
+    int rc = plan_image(descs[0], &imgs[0], 1, hs_pref, false);   // the stack takes the slice index
     void* ws = nullptr;
     size_t ws_bytes = 0;
     if (rc == RSG_OK && imgs[0].path == kPathFused && int64_t(imgs[0].ntasks) * D <= (int64_t(1) << 30)) {

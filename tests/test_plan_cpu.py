@@ -187,3 +187,33 @@ def test_table_first_layout_field():
     b = _run_planner_code("print(rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3))[2])\n",
                           "1 1 %d %d 0 %d 256 1\n" % (R, R, 1 << 40))
     assert int(a) != int(b)
+
+
+def test_channel_planar_plan():
+    """Channel-planar tasks: one task per 64 pixels of one channel; the row
+    span (and so the tile) is that of a one-channel image."""
+    try:
+        rsg.rsg_tune_columns(1)
+        hs1, t1, lds1 = rsg.rsg_plan_shape(_desc(2048, 2048, C=3, dt=rsg.RSG_U8, sigma=8.0, K=4))
+        rsg.rsg_tune_columns(3)
+        hs3, t3, lds3 = rsg.rsg_plan_shape(_desc(2048, 2048, C=3, dt=rsg.RSG_U8, sigma=8.0, K=4))
+        assert t1 == -(-2048 * 3 // 64) * -(-2048 // hs1)
+        assert t3 == 3 * (2048 // 64) * -(-2048 // hs3)
+        h, t, _ = rsg.rsg_plan_shape(_desc(100, 70, C=1, dt=rsg.RSG_U8))   # one channel: unchanged
+        assert t == 2 * -(-100 // h)
+        with pytest.raises(rsg.RsgError):
+            rsg.rsg_tune_columns(4)
+    finally:
+        rsg.rsg_tune_columns(0)
+
+
+def test_too_wide_for_interleaved_and_two_pass_takes_planar_tasks():
+    """Four channels with boxes too wide for both the interleaved span and
+    the two-pass window: the planner falls back to channel-planar tasks
+    (was RSG_EUNSUPPORTED)."""
+    _run_planner_code(
+        "hs, tasks, lds = rsg.rsg_plan_shape(_desc(1024, 1024, C=4, dt=rsg.RSG_U8, sigma=64.0, K=5))\n"
+        "assert tasks == 4 * (1024 // 64) * -(-1024 // hs), (hs, tasks)\n"
+        "rsg.rsg_tune_path(rsg.RSG_PATH_FUSED_ONE_WAVE)\n"
+        "with pytest.raises(rsg.RsgError):\n"
+        "    rsg.rsg_plan_shape(_desc(1024, 1024, C=4, dt=rsg.RSG_U8, sigma=64.0, K=5))\n")
