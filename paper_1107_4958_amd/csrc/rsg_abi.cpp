@@ -72,14 +72,17 @@ int plan_batch(const rsg_image_desc* d, int n, std::vector<ImgParams>& imgs, std
     }
     if (total > (int64_t(1) << 30)) return set_error(RSG_EUNSUPPORTED, "batch too large");
     tasks.reserve(size_t(total));
-    // interleave the images' tasks largest-image-first so long images start
-    // early; per-image results do not depend on the order
+    // queue the longest tasks first (rows streamed x row span scanned per
+    // task), so the last workgroups to finish run short tasks; per-image
+    // results do not depend on the order
+    auto task_cost = [&](int i) {
+        const ImgParams& ip = imgs[i];
+        const int64_t cols = int64_t(kWave) * std::max(1, ip.nc) + int64_t(2 * ip.R + 1) * (ip.pstride > 1 ? 1 : ip.C);
+        return int64_t(std::min(ip.hs, ip.H) + 2 * ip.R + 1) * cols;
+    };
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return int64_t(imgs[a].ntasks) * (imgs[a].hs + 2 * imgs[a].R) >
-               int64_t(imgs[b].ntasks) * (imgs[b].hs + 2 * imgs[b].R);
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return task_cost(a) > task_cost(b); });
     for (int i : order)
         if (imgs[i].path == kPathFused)       // two-pass images are launched on their own
             for (int t = 0; t < imgs[i].ntasks; ++t) tasks.push_back(BatchTask{i, t});
