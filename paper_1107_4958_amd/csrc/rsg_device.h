@@ -749,7 +749,7 @@ __device__ __forceinline__ void stream_task(const ImgParams& ip, const TaskGeom&
 // for the prefetched loads stay exact.
 // --------------------------------------------------------------------------
 template <class Tr, int C, int SEG, int NPL, int KT, bool EDGE, int NC = 1, bool ZX = false, int NW_ = kCoWaves,
-          int RB_ = co_rows(NC)>
+          int RB_ = co_rows(NC), bool TS = false>
 __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGeom& tg, uint32_t* lds)
 {
     using Acc = typename Tr::Acc;
@@ -959,9 +959,11 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
         return d;
     };
 
+    constexpr int NST = TS ? 2 : RB;           // stores per wave per step
+    static_assert(!TS || (NC == 1 && es == 4 && RB == 8 && !EDGE && !ZX), "staged stores: FP32, interior, one column per lane");
     auto dropped_stores = [&](int base) {      // distinct offsets: not merged by the compiler
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
+        for (int j = 0; j < NST; ++j) {
             if constexpr (kInt) __builtin_amdgcn_raw_buffer_store_b8(uint8_t(0), rs_dst, kDropOffset - 64 * (base + j), 0, kStorePolicy<1>);
             else store_out<Tr>(rs_dst, kDropOffset - 64 * (base + j), 0, 0.0f);
         }
@@ -1151,10 +1153,9 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
             }
         }
         // the lane's NC results of block row i from its taps rv, stored
-        auto combine_store = [&](const Acc (&rv)[2 * KT][NC], int i) {
-            const int vo = int(ocol + uint32_t(soff[i]));
+        // the stored bits of the lane's NC results of block row i from its taps rv
+        auto combine = [&](const Acc (&rv)[2 * KT][NC], int i, uint32_t (&w)[NC]) {
             const float dcy = zext ? dc_rows(tg.y0 + kb + i) : dc;
-            uint32_t w[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if constexpr (kInt) {
@@ -1170,9 +1171,53 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
                     w[c] = out_bits<Tr>(o);
                 }
             }
+        };
+        auto combine_store = [&](const Acc (&rv)[2 * KT][NC], int i) {
+            const int vo = int(ocol + uint32_t(soff[i]));
+            uint32_t w[NC];
+            combine(rv, i, w);
             store_group<Tr, NC>(rs_dst, vo, w, lane_full, nlive, ovec);
         };
-        if (ostep == 1) {
+        if constexpr (TS) {
+            // Staged stores: the wave's RB x 64 results go through its row
+            // tile (unused until the next step's row pass; one wave's LDS
+            // accesses complete in order) and leave as 16-byte stores, four
+            // whole 256-byte row pieces per instruction instead of one.
+            constexpr int HB = (8 * KT <= 48) ? 4 : 2;
+            static_assert(G * PP >= RB * kWave, "the row tile holds the staged results");
+            uint32_t* stg = reinterpret_cast<uint32_t*>(Pt);
+#pragma unroll
+            for (int h = 0; h < RB / HB; ++h) {
+                __builtin_amdgcn_sched_barrier(0);
+                Acc rv[HB][2 * KT][NC];
+#pragma unroll
+                for (int k = 0; k < KT; ++k) {
+#pragma unroll
+                    for (int i = 0; i < HB; ++i) {
+                        lds_get<Acc, NC>(ring + (ta[k] + h * HB + i) * RP + lane * NC, rv[i][2 * k]);
+                        lds_get<Acc, NC>(ring + (tb[k] + h * HB + i) * RP + lane * NC, rv[i][2 * k + 1]);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < HB; ++i) {
+                    uint32_t w[1];
+                    combine(rv[i], h * HB + i, w);
+                    stg[(h * HB + i) * kWave + lane] = w[0];
+                }
+            }
+            wave_lds_fence();
+            // piece idx = lane + 64 j: block row idx / 16, columns 4 (idx % 16) ..
+            const uint32_t sb0 = uint32_t(tg.o0 * es);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int idx = lane + kWave * j;
+                const int k = kb + (idx >> 4);
+                const v4u val = *reinterpret_cast<const v4u*>(stg + idx * 4);
+                const int vo = (unsigned(k) < unsigned(tg.hs)) ? int(sb0 + uint32_t(k) * dstr + uint32_t(idx & 15) * 16u)
+                                                               : kDropOffset;
+                __builtin_amdgcn_raw_buffer_store_b128(val, rs_dst, vo, 0, kStorePolicy<16>);
+            }
+        } else if (ostep == 1) {
             // every row: the taps of HB rows at a time (fewer live registers)
             constexpr int HB = (8 * KT * NC <= 48) ? 4 : ((4 * KT * NC <= 48) ? 2 : 1);
             static_assert(RB % HB == 0, "whole sub-blocks");
@@ -1256,6 +1301,16 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
             if (ip.boundary == RSG_ZERO) {
                 if (interior) stream_task_co<Tr, C, SEG, NPL, KT, false, NC, true>(ip, tg, lds);
                 else stream_task_co<Tr, C, SEG, NPL, KT, true, NC, true>(ip, tg, lds);
+                return;
+            }
+        }
+        // FP32 with four or five taps: interior tasks whose output rows are
+        // 16-byte aligned store through the row tile (3 % faster there; at
+        // three taps, and for uint8, the extra LDS traffic costs more)
+        if constexpr (NC == 1 && Tr::kSize == 4 && KT >= 4) {
+            const uintptr_t db = reinterpret_cast<uintptr_t>(ip.dst) + uintptr_t(tg.slice_off);
+            if (interior && ip.step <= 1 && ip.pstride <= 1 && (db % 16) == 0 && ((ip.dst_stride * 4) % 16) == 0) {
+                stream_task_co<Tr, C, SEG, NPL, KT, false, NC, false, kCoWaves, co_rows(NC), true>(ip, tg, lds);
                 return;
             }
         }
