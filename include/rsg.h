@@ -299,9 +299,10 @@ int rsg_server_destroy(rsg_server* s);
  * windows) and the LDS is the larger pass's.  Host-only: d->src and d->dst
  * are compared but never dereferenced.  Segment heights come from the tuning
  * table named by the environment variable RSG_TUNE_TABLE (read once, lines
- * "dtype C rlo rhi nlo nhi hs [nc [lo]]", with R the largest box
+ * "dtype C rlo rhi nlo nhi hs [nc [lo [st]]]", with R the largest box
  * half-width, n the number of 64-sample strips times H, nc the columns per
- * lane of rsg_tune_columns and lo the first layout of rsg_tune_layout),
+ * lane of rsg_tune_columns, lo the first layout of rsg_tune_layout and st
+ * the store form of rsg_tune_stores),
  * else from a built-in rule.  This is
  * the image's own plan; in a batch, uint8 images may get longer segments
  * (same results).  Any output pointer may be NULL.
@@ -356,6 +357,17 @@ int rsg_tune_columns(int32_t columns);
  * Results agree to FP32 rounding (bit-identical for
  * uint8).  For the autotuner and tests.  Errors: RSG_EINVAL (not in 0..3). */
 int rsg_tune_layout(int32_t first);
+
+/* Process-wide output store form of the fused kernel for every later FP32
+ * plan with one column per lane: 0 lets the planner choose (the tuning
+ * table's optional last field, else staged stores where the kernel has four
+ * or five taps), 1 one store per lane and output row (4 bytes), 2 staged
+ * stores: each wave writes its 8 x 64 results to its own LDS row tile and
+ * stores them as 16-byte pieces of rows, on tasks whose column span lies
+ * inside the image and whose output rows are 16-byte aligned (other tasks
+ * keep the per-lane stores).  Results are bit-identical either way.  For the
+ * autotuner and tests.  Errors: RSG_EINVAL (not in 0..2). */
+int rsg_tune_stores(int32_t form);
 
 /* ---------------------------------------------------------------------- */
 /* Measurement.                                                            */

@@ -10,7 +10,7 @@ Entry points carry the C names (``rsg_fit_boxes``, ``rsg_fit_boxes_ex``,
 ``rsg_gauss_filter``, ``rsg_gauss_filter_noalloc``, ``rsg_box_filter``, ``rsg_gauss_filter_strided``,
 ``rsg_gauss_filter_3d``, ``rsg_filter_batch_workspace``, ``rsg_filter_batch``,
 ``rsg_server_create``, ``rsg_submit``, ``rsg_poll``, ``rsg_server_destroy``,
-``rsg_plan_shape``, ``rsg_tune_override``, ``rsg_tune_path``, ``rsg_tune_columns``, ``rsg_tune_layout``,
+``rsg_plan_shape``, ``rsg_tune_override``, ``rsg_tune_path``, ``rsg_tune_columns``, ``rsg_tune_layout``, ``rsg_tune_stores``,
 ``rsg_stream_copy``, ``rsg_last_error``); ``filter_tensor``, ``filter_strided_tensor``,
 ``filter_volume_tensor`` and ``filter_batch_tensors`` wrap them for torch
 tensors.
@@ -110,7 +110,7 @@ class rsg_req_stats(ctypes.Structure):
 
 SYMBOLS = ("rsg_fit_boxes", "rsg_gauss_filter", "rsg_filter_batch_workspace", "rsg_filter_batch",
            "rsg_server_create", "rsg_submit", "rsg_poll", "rsg_server_destroy", "rsg_plan_shape",
-           "rsg_tune_override", "rsg_tune_path", "rsg_tune_columns", "rsg_tune_layout", "rsg_fit_boxes_ex", "rsg_box_filter", "rsg_gauss_filter_strided",
+           "rsg_tune_override", "rsg_tune_path", "rsg_tune_columns", "rsg_tune_layout", "rsg_tune_stores", "rsg_fit_boxes_ex", "rsg_box_filter", "rsg_gauss_filter_strided",
            "rsg_gauss_filter_3d", "rsg_gauss_filter_noalloc", "rsg_stream_copy", "rsg_last_error")
 
 
@@ -150,6 +150,7 @@ def _load():
     lib.rsg_tune_path.argtypes = [ctypes.c_int32]
     lib.rsg_tune_columns.argtypes = [ctypes.c_int32]
     lib.rsg_tune_layout.argtypes = [ctypes.c_int32]
+    lib.rsg_tune_stores.argtypes = [ctypes.c_int32]
     lib.rsg_last_error.argtypes = []
     lib.rsg_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS[:-1]:
@@ -277,6 +278,10 @@ def rsg_tune_columns(columns: int) -> None:
 
 def rsg_tune_layout(first: int) -> None:
     _check(_lib.rsg_tune_layout(int(first)))
+
+
+def rsg_tune_stores(form: int) -> None:
+    _check(_lib.rsg_tune_stores(int(form)))
 
 
 # ---------------------------------------------------------------------------

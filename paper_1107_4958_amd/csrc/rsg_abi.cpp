@@ -132,6 +132,15 @@ int rsg_tune_layout(int32_t first)
     return RSG_OK;
 }
 
+int rsg_tune_stores(int32_t form)
+{
+    using namespace rsg;
+    if (form < 0 || form > 2)
+        return set_error(RSG_EINVAL, "store form must be 0 (planner), 1 (one per lane and row) or 2 (staged)");
+    set_stores_override(form);
+    return RSG_OK;
+}
+
 int rsg_tune_override(int32_t seg_height)
 {
     using namespace rsg;

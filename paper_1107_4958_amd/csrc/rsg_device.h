@@ -1304,12 +1304,12 @@ __device__ __forceinline__ void run_task(const ImgParams& ip, int task, uint32_t
                 return;
             }
         }
-        // FP32 with four or five taps: interior tasks whose output rows are
-        // 16-byte aligned store through the row tile (3 % faster there; at
-        // three taps, and for uint8, the extra LDS traffic costs more)
-        if constexpr (NC == 1 && Tr::kSize == 4 && KT >= 4) {
+        // FP32 images planned with staged stores: interior tasks whose
+        // output rows are 16-byte aligned store through the row tile
+        if constexpr (NC == 1 && Tr::kSize == 4) {
             const uintptr_t db = reinterpret_cast<uintptr_t>(ip.dst) + uintptr_t(tg.slice_off);
-            if (interior && ip.step <= 1 && ip.pstride <= 1 && (db % 16) == 0 && ((ip.dst_stride * 4) % 16) == 0) {
+            if (ip.staged && interior && ip.step <= 1 && ip.pstride <= 1 && (db % 16) == 0 &&
+                ((ip.dst_stride * 4) % 16) == 0) {
                 stream_task_co<Tr, C, SEG, NPL, KT, false, NC, false, kCoWaves, co_rows(NC), true>(ip, tg, lds);
                 return;
             }

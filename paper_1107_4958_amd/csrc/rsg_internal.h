@@ -85,6 +85,8 @@ struct ImgParams {
     int32_t co;                    // fused path: 1 = cooperative workgroups of kCoWaves waves, 0 = one wave
     int32_t nc;                    // cooperative form: consecutive columns per lane (1, or wide_nc(C))
     int32_t ovec;                  // the destination allows one vector store per lane's columns
+    int32_t staged;                // FP32, one column per lane: interior tasks with 16-byte aligned
+                                   // output rows stage each wave's results in LDS for 16-byte stores
     int32_t pnpl[2];               // samples per lane of pass A, pass B
     int32_t pst[2];                // staging tiles of pass A, pass B (1 or 2)
     uint32_t plds[2];              // LDS bytes per workgroup of pass A, pass B
@@ -155,6 +157,9 @@ void set_path_override(int path);
 void set_nc_override(int nc);
 // Process-wide first row-scan layout the planner tries (0: the first that fits).
 void set_layout_override(int lo);
+// Process-wide output store form (0: the table, else the built-in rule;
+// 1: one store per lane and row; 2: staged 16-byte stores).
+void set_stores_override(int st);
 
 // Launchers (rsg_kernels.hip).
 int launch_single(const ImgParams& ip, hipStream_t stream);

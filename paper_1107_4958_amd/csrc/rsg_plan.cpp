@@ -43,13 +43,14 @@ int lcm_i(int a, int b) { return a / gcd_i(a, b) * b; }
 // column per lane, 0 or none the built-in rule; lo > 0 starts the search for
 // a row-scan layout at layout lo (wider rows per group, fewer rows), 0 or
 // none at the first.
-struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs, nc, lo; };
+struct TuneEntry { int dtype, C, rlo, rhi; int64_t nlo, nhi; int hs, nc, lo, st; };
 std::once_flag g_tune_once;
 std::vector<TuneEntry> g_tune;
 std::atomic<int> g_hs_override{0};
 std::atomic<int> g_path_override{0};
 std::atomic<int> g_nc_override{0};
 std::atomic<int> g_lo_override{0};
+std::atomic<int> g_st_override{0};
 
 // Two-pass geometry: the smallest chunk (64 NPL samples) that holds the
 // window head (2R + 1) C and fits the LDS with one staging tile (0 if none
@@ -88,12 +89,13 @@ void load_tune_table()
         if (is >> e.dtype >> e.C >> e.rlo >> e.rhi >> e.nlo >> e.nhi >> e.hs && (e.hs > 0 || e.hs == -1)) {
             if (!(is >> e.nc) || e.nc < 0) e.nc = 0;
             if (!(is >> e.lo) || e.lo < 0 || e.lo >= kLayouts) e.lo = 0;
+            if (!(is >> e.st) || e.st < 0 || e.st > 2) e.st = 0;
             g_tune.push_back(e);
         }
     }
 }
 
-bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs, int* nc, int* lo)
+bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs, int* nc, int* lo, int* st)
 {
     const int ov = g_hs_override.load(std::memory_order_relaxed);
     if (ov > 0) { *hs = ov; return true; }
@@ -103,6 +105,7 @@ bool tuned_hs(int dtype, int C, int R, int64_t n, int* hs, int* nc, int* lo)
             *hs = e.hs;
             *nc = e.nc;
             *lo = e.lo;
+            *st = e.st;
             return true;
         }
     return false;
@@ -153,6 +156,7 @@ void set_hs_override(int hs) { g_hs_override.store(hs > 0 ? hs : 0, std::memory_
 void set_path_override(int path) { g_path_override.store(path, std::memory_order_relaxed); }
 void set_nc_override(int nc) { g_nc_override.store(nc > 0 ? nc : 0, std::memory_order_relaxed); }
 void set_layout_override(int lo) { g_lo_override.store(lo > 0 ? lo : 0, std::memory_order_relaxed); }
+void set_stores_override(int st) { g_st_override.store(st > 0 ? st : 0, std::memory_order_relaxed); }
 
 int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref, bool planar_ok)
 {
@@ -241,8 +245,8 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref, bo
         p.plds[1] = pass_lds_bytes(p.pnpl[1], 2 * R + 1, p.pst[1], p.ptr[1]);
     }
     const int ov = g_path_override.load(std::memory_order_relaxed);
-    int hs_t = 0, nc_t = 0, lo_t = 0;
-    const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t, &nc_t, &lo_t);
+    int hs_t = 0, nc_t = 0, lo_t = 0, st_t = 0;
+    const bool tabled = tuned_hs(d.dt, C, R, (WC + kWave - 1) / kWave * d.H, &hs_t, &nc_t, &lo_t, &st_t);
     const int lo_ov = g_lo_override.load(std::memory_order_relaxed);
     const int lo_first = lo_ov > 0 ? lo_ov : lo_t;      // first row-scan layout tried
     bool two = two_ok && (tabled ? hs_t < 0 : R * C >= kTwoPassMinRC);
@@ -347,6 +351,12 @@ int plan_image(const rsg_image_desc& d, ImgParams* ip, int step, int hs_pref, bo
         const int gb = nc * es;
         const uintptr_t da = reinterpret_cast<uintptr_t>(d.dst);
         p.ovec = (es == 4) || (nc > 1 && (gb & (gb - 1)) == 0 && da % gb == 0 && (ds * es) % gb == 0);
+    }
+    {   // output stores of FP32 cooperative one-column tasks: the override,
+        // else the table, else staged where the kernel has four or five taps
+        const int st_ov = g_st_override.load(std::memory_order_relaxed);
+        const int st_want = st_ov > 0 ? st_ov : st_t;
+        p.staged = (es == 4 && co && nc == 1 && !planar && step == 1) ? int(st_want == 2 || (st_want == 0 && p.kt >= 4)) : 0;
     }
     p.lds_one = tile_lds_bytes(seg, npl, p.L);
     p.lds_bytes = p.co ? tile_lds_bytes_co(seg, npl, p.Lco, p.nc) : p.lds_one;

@@ -1,5 +1,6 @@
-"""Staged stores of the cooperative fused kernel: FP32 images with four or
-five taps whose interior tasks write 16-byte-aligned output rows stage each
+"""Staged stores of the cooperative fused kernel: FP32 images planned with
+them (the tuning table's store form, rsg_tune_stores, else four or five
+taps), whose interior tasks write 16-byte-aligned output rows, stage each
 wave's 8 x 64 results in LDS and store them as 16-byte row pieces.  Checked
 against the oracle (FP32 max|err| / max|oracle| <= 1e-5) on ragged heights
 (tasks that end inside a wave's block), single rows, several channels and a
@@ -92,3 +93,23 @@ def test_staged_batch_identical_to_alone():
         alone = rsg.filter_tensor(srcs[i], s[3], s[4])
         torch.cuda.synchronize()
         assert np.array_equal(from_device(dsts[i], "f32").view(np.uint32), from_device(alone, "f32").view(np.uint32)), i
+
+
+@pytest.mark.parametrize("H,W,C,sigma,K", [(203, 1000, 1, 5.0, 3), (77, 640, 3, 2.0, 3), (300, 2048, 1, 8.0, 5),
+                                           (100, 777, 2, 3.0, 4)])
+def test_forced_store_forms(H, W, C, sigma, K):
+    """rsg_tune_stores(2) (staged, three taps included) against the oracle,
+    and bit-identical to rsg_tune_stores(1) (one store per lane and row)."""
+    import paper_1107_4958_amd as rsg
+    from gpu_util import gpu_filter
+    img = synthimg.image(H, W, C, "f32", seed=H * 3 + K)
+    outs = []
+    try:
+        for form in (2, 1):
+            rsg.rsg_tune_stores(form)
+            if form == 2:
+                par._check(img, "f32", sigma, K, oracle.REPLICATE)
+            outs.append(gpu_filter(img, "f32", sigma, K))
+    finally:
+        rsg.rsg_tune_stores(0)
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))

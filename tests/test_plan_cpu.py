@@ -189,6 +189,21 @@ def test_table_first_layout_field():
     assert int(a) != int(b)
 
 
+def test_table_store_form_field():
+    """The table's store-form field (and rsg_tune_stores) is read with the
+    plan: staged stores use the wave's existing row tile, so the segments,
+    tasks and LDS are those of the per-lane stores; out-of-range values are
+    refused."""
+    R = int(max(rsg.rsg_fit_boxes(8.0, 3).r[:3]))
+    shapes = [_run_planner_code("print(*rsg.rsg_plan_shape(_desc(4096, 4096, sigma=8.0, K=3)))\n",
+                                "1 1 %d %d 0 %d 256 1 0 %d\n" % (R, R, 1 << 40, st)) for st in (1, 2)]
+    assert shapes[0] == shapes[1] and shapes[0].split()[:2] == ["256", str(64 * 16)], shapes
+    _run_planner_code(
+        "for form in (0, 1, 2, 0):\n    rsg.rsg_tune_stores(form)\n"
+        "for bad in (-1, 3):\n    with pytest.raises(rsg.RsgError):\n        rsg.rsg_tune_stores(bad)\n",
+        "1 1 %d %d 0 %d 256 1 0 2\n" % (R, R, 1 << 40))
+
+
 def test_channel_planar_plan():
     """Channel-planar tasks: one task per 64 pixels of one channel; the row
     span (and so the tile) is that of a one-channel image."""
