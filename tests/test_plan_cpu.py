@@ -232,3 +232,13 @@ def test_too_wide_for_interleaved_and_two_pass_takes_planar_tasks():
         "rsg.rsg_tune_path(rsg.RSG_PATH_FUSED_ONE_WAVE)\n"
         "with pytest.raises(rsg.RsgError):\n"
         "    rsg.rsg_plan_shape(_desc(1024, 1024, C=4, dt=rsg.RSG_U8, sigma=64.0, K=5))\n")
+
+
+def test_autotune_store_field():
+    """The tuner records a measured store form only where it departs from
+    the planner's rule at the measured tap count (staged at four and five
+    taps): a staged win at three taps, a per-lane win at four or five."""
+    from paper_1107_4958_amd.autotune import store_field
+    assert [store_field(st, 3) for st in (0, 1, 2)] == [0, 0, 2]
+    for K in (4, 5):
+        assert [store_field(st, K) for st in (0, 1, 2)] == [0, 1, 0]
