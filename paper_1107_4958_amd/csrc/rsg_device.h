@@ -1152,7 +1152,6 @@ __device__ __forceinline__ void stream_task_co(const ImgParams& ip, const TaskGe
                 if (++rr == ostep) { rr = 0; ++qrow; }
             }
         }
-        // the lane's NC results of block row i from its taps rv, stored
         // the stored bits of the lane's NC results of block row i from its taps rv
         auto combine = [&](const Acc (&rv)[2 * KT][NC], int i, uint32_t (&w)[NC]) {
             const float dcy = zext ? dc_rows(tg.y0 + kb + i) : dc;
